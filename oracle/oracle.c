@@ -1,0 +1,294 @@
+/*
+ * CPU oracle: plain classic time-stepping, one level (sub-timestep) at a time,
+ * reading the previous level from one buffer and writing the next into another.
+ * Test infrastructure only -- see oracle.h.  Every update below is written out
+ * from the paper's appendices in the order the equations state it; OpenMP only
+ * splits the loop over grid points (no reductions, so the result does not depend
+ * on the thread count).  Build with -ffp-contract=off and no fast-math.
+ */
+#include "oracle.h"
+
+#include <math.h>
+#include <omp.h>
+#include <stdlib.h>
+#include <string.h>
+#include <time.h>
+
+/* ------------------------------------------------------------------------ */
+/* Boundary handling                                                          */
+/* ------------------------------------------------------------------------ */
+
+/* Value of variable v at grid index j, which may lie outside [0, n).
+ * Periodic: the stencil at point 0 reaches points n-1, n-2 (Appendix C).
+ * Dirichlet: the end states are held at their ends for every (sub)level
+ * (Appendix D: "the spatial boundary conditions are these values at their
+ * respective ends of the tube"). */
+static double at(const oracle_problem *p, const double *a, int64_t j, int v)
+{
+    const int64_t n = p->n;
+    if (j >= 0 && j < n) return a[(int64_t)v * n + j];
+    if (p->bc == ORACLE_PERIODIC) {
+        int64_t k = j % n;
+        if (k < 0) k += n;
+        return a[(int64_t)v * n + k];
+    }
+    return j < 0 ? p->bc_left[v] : p->bc_right[v];
+}
+
+/* ------------------------------------------------------------------------ */
+/* Heat equation, Appendix B, Eq. Heatdisc:                                   */
+/*   T_i^{m+1} = Fo (T_{i+1}^m + T_{i-1}^m) + (1 - 2 Fo) T_i^m,               */
+/*   Fo = alpha dt / dx^2.                                                    */
+/* ------------------------------------------------------------------------ */
+
+static void heat_level(const oracle_problem *p, const double *cur, double *nxt,
+                       double fo, double c0)
+{
+    const int64_t n = p->n;
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        double s = at(p, cur, i + 1, 0) + at(p, cur, i - 1, 0);
+        nxt[i] = fo * s + c0 * cur[i];
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Kuramoto-Sivashinsky, Appendix C.  Right-hand side of Eq. KSDisc           */
+/*   f_i(v) = -( (v_{i+1}^2 - v_{i-1}^2)/(4 dx)                               */
+/*              + (v_{i+1} + v_{i-1} - 2 v_i)/dx^2                            */
+/*              + (v_{i+2} - 4 v_{i+1} + 6 v_i - 4 v_{i-1} + v_{i-2})/dx^4 )   */
+/* (the central second difference carries -2 v_i), with the four-point       */
+/* terms grouped in symmetric pairs.                                          */
+/* ------------------------------------------------------------------------ */
+
+static double ks_rhs(const oracle_problem *p, const double *v, int64_t i,
+                     double c1, double c2, double c4)
+{
+    double vm2 = at(p, v, i - 2, 0), vm1 = at(p, v, i - 1, 0), v0 = v[i];
+    double vp1 = at(p, v, i + 1, 0), vp2 = at(p, v, i + 2, 0);
+    double advect = (vp1 * vp1 - vm1 * vm1) * c1;
+    double diff2 = ((vp1 + vm1) - 2.0 * v0) * c2;
+    double diff4 = (((vp2 + vm2) - 4.0 * (vp1 + vm1)) + 6.0 * v0) * c4;
+    return -((advect + diff2) + diff4);
+}
+
+/* Predictor, Eq. RKm: u^{m+1/2} = u^m + (dt/2) f(u^m). */
+static void ks_predictor(const oracle_problem *p, const double *u, double *half,
+                         double c1, double c2, double c4, double hdt)
+{
+    const int64_t n = p->n;
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i)
+        half[i] = u[i] + hdt * ks_rhs(p, u, i, c1, c2, c4);
+}
+
+/* Final, Eq. RKf: u^{m+1} = u^m + dt f(u^{m+1/2}). */
+static void ks_final(const oracle_problem *p, const double *u, const double *half,
+                     double *nxt, double c1, double c2, double c4, double dt)
+{
+    const int64_t n = p->n;
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i)
+        nxt[i] = u[i] + dt * ks_rhs(p, half, i, c1, c2, c4);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Euler equations, Appendix D.  Q = (rho, rho u, E) with E the total energy   */
+/* per volume; F(Q) = (rho u, rho u^2 + P, u (E + P)); P from Eq. EulerP.      */
+/* ------------------------------------------------------------------------ */
+
+typedef struct { double gm1, gamma; int limiter; } euler_consts;
+
+/* Eq. EulerP: P = (gamma - 1)(E - rho u^2 / 2), evaluated as (m u)/2 with u = m/rho. */
+static double pressure(const double q[3], const euler_consts *c)
+{
+    double u = q[1] / q[0];
+    return c->gm1 * (q[2] - 0.5 * (q[1] * u));
+}
+
+static double min_d(double a, double b) { return a < b ? a : b; }
+
+/* Flux through the interface between cells b and c = b + 1, from the four cells
+ * a = b-1, b, c, d = c+1 (the interface flux of Appendix D). */
+static void interface_flux(const double qa[3], const double qb[3], const double qc[3],
+                           const double qd[3], const euler_consts *c, double flux[3])
+{
+    /* Eq. Pratio: P_{r,j} = (P_{j+1} - P_j) / (P_j - P_{j-1}) at j = b and j = c. */
+    double pa = pressure(qa, c), pb = pressure(qb, c), pc = pressure(qc, c), pd = pressure(qd, c);
+    double pr_b = (pc - pb) / (pb - pa);
+    double pr_c = (pd - pc) / (pc - pb);
+    double ql[3], qr[3];
+    int v;
+
+    if (c->limiter == 0) {
+        /* Eq. limitleft: Q^L = Q_b + min(Pr_b, 1)/2 (Q_c - Q_b) if 0 < Pr_b < inf. */
+        int okl = pr_b > 0.0 && pr_b < INFINITY;
+        /* Eq. limitright: Q^R = Q_c + min(1/Pr_c, 1)/2 (Q_b - Q_c) if 0 < 1/Pr_c < inf. */
+        double ir = 1.0 / pr_c;
+        int okr = ir > 0.0 && ir < INFINITY;
+        double sl = 0.5 * min_d(pr_b, 1.0), sr = 0.5 * min_d(ir, 1.0);
+        for (v = 0; v < 3; ++v) {
+            ql[v] = okl ? qb[v] + sl * (qc[v] - qb[v]) : qb[v];
+            qr[v] = okr ? qc[v] + sr * (qb[v] - qc[v]) : qc[v];
+        }
+    } else {
+        /* Reciprocal orientation: the ratio backward/forward on the left side. */
+        double il = 1.0 / pr_b;
+        int okl = il > 0.0 && il < INFINITY;
+        int okr = pr_c > 0.0 && pr_c < INFINITY;
+        double sl = 0.5 * min_d(il, 1.0), sr = 0.5 * min_d(pr_c, 1.0);
+        for (v = 0; v < 3; ++v) {
+            ql[v] = okl ? qb[v] + sl * (qc[v] - qb[v]) : qb[v];
+            qr[v] = okr ? qc[v] + sr * (qb[v] - qc[v]) : qc[v];
+        }
+    }
+
+    /* Physical fluxes of the two reconstructed states, Eq. EulerF. */
+    double ul = ql[1] / ql[0], ur = qr[1] / qr[0];
+    double pl = c->gm1 * (ql[2] - 0.5 * (ql[1] * ul));
+    double prr = c->gm1 * (qr[2] - 0.5 * (qr[1] * ur));
+    double fl[3] = { ql[1], ql[1] * ul + pl, ul * (ql[2] + pl) };
+    double fr[3] = { qr[1], qr[1] * ur + prr, ur * (qr[2] + prr) };
+
+    /* Roe-averaged state and spectral radius r_sp = sqrt(gamma P_sp/rho_sp) + |u_sp|. */
+    double sql = sqrt(ql[0]), sqr = sqrt(qr[0]);
+    double rho_s = sqrt(ql[0] * qr[0]);
+    double den = sql + sqr;
+    double u_s = (sql * ul + sqr * ur) / den;
+    double e_s = (sql * ql[2] + sqr * qr[2]) / den;
+    double p_s = c->gm1 * (e_s - 0.5 * ((rho_s * u_s) * u_s));
+    double r_sp = sqrt((c->gamma * p_s) / rho_s) + fabs(u_s);
+
+    /* Flux = (F(Q^R) + F(Q^L) + r_sp (Q^L - Q^R)) / 2. */
+    for (v = 0; v < 3; ++v)
+        flux[v] = 0.5 * ((fr[v] + fl[v]) + r_sp * (ql[v] - qr[v]));
+}
+
+static void load_cell(const oracle_problem *p, const double *q, int64_t j, double out[3])
+{
+    for (int v = 0; v < 3; ++v) out[v] = at(p, q, j, v);
+}
+
+/* One RK2 stage of the finite-volume update: out_i = base_i + coef (F_{i-1/2} - F_{i+1/2}),
+ * fluxes evaluated from `src`.  The conservation law (Eq. EulerGeneral) fixes the sign:
+ * the flux leaving through i+1/2 is subtracted. */
+static void euler_stage(const oracle_problem *p, const double *src, const double *base,
+                        double *out, double coef, const euler_consts *c)
+{
+    const int64_t n = p->n;
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        double q[5][3];
+        for (int k = 0; k < 5; ++k) load_cell(p, src, i - 2 + k, q[k]);
+        double fm[3], fp[3];
+        interface_flux(q[0], q[1], q[2], q[3], c, fm);   /* i - 1/2 */
+        interface_flux(q[1], q[2], q[3], q[4], c, fp);   /* i + 1/2 */
+        for (int v = 0; v < 3; ++v)
+            out[(int64_t)v * n + i] = base[(int64_t)v * n + i] + coef * (fm[v] - fp[v]);
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Driver                                                                     */
+/* ------------------------------------------------------------------------ */
+
+static int nvars_of(int scheme) { return scheme == ORACLE_EULER ? 3 : 1; }
+
+static int valid(const oracle_problem *p)
+{
+    if (!p) return 0;
+    if (p->scheme < ORACLE_HEAT || p->scheme > ORACLE_EULER) return 0;
+    if (p->bc != ORACLE_PERIODIC && p->bc != ORACLE_DIRICHLET) return 0;
+    if (p->n < 1 || p->nsteps < 0) return 0;
+    if (!(p->dt > 0.0) || !(p->dx > 0.0)) return 0;
+    return 1;
+}
+
+int oracle_threads(int nthreads)
+{
+    int t = 1;
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+    else omp_set_num_threads(omp_get_num_procs());
+#pragma omp parallel
+    {
+#pragma omp single
+        t = omp_get_num_threads();
+    }
+    return t;
+}
+
+static double now_s(void)
+{
+    struct timespec ts;
+    clock_gettime(CLOCK_MONOTONIC, &ts);
+    return (double)ts.tv_sec + 1e-9 * (double)ts.tv_nsec;
+}
+
+int oracle_solve_timed(const oracle_problem *p, double *state, int nthreads, double *seconds)
+{
+    if (!valid(p) || !state) return -1;
+    const int64_t n = p->n;
+    const int nv = nvars_of(p->scheme);
+    const size_t bytes = (size_t)nv * (size_t)n * sizeof(double);
+    double *a = state;
+    double *b = (double *)malloc(bytes);
+    double *h = (double *)malloc(bytes);
+    if (!b || !h) { free(b); free(h); return -1; }
+    oracle_threads(nthreads);
+
+    double t0 = now_s();
+    if (p->scheme == ORACLE_HEAT) {
+        double fo = (p->alpha * p->dt) / (p->dx * p->dx);
+        double c0 = 1.0 - 2.0 * fo;
+        for (int64_t m = 0; m < p->nsteps; ++m) {
+            heat_level(p, a, b, fo, c0);
+            double *t = a; a = b; b = t;
+        }
+    } else if (p->scheme == ORACLE_KS) {
+        double c1 = 1.0 / (4.0 * p->dx);
+        double c2 = 1.0 / (p->dx * p->dx);
+        double c4 = c2 * c2;
+        double hdt = 0.5 * p->dt;
+        for (int64_t m = 0; m < p->nsteps; ++m) {
+            ks_predictor(p, a, h, c1, c2, c4, hdt);
+            ks_final(p, a, h, b, c1, c2, c4, p->dt);
+            double *t = a; a = b; b = t;
+        }
+    } else {
+        euler_consts c;
+        c.gm1 = p->gamma - 1.0;
+        c.gamma = p->gamma;
+        c.limiter = p->limiter;
+        double lam = p->dt / p->dx;
+        double hlam = 0.5 * lam;
+        for (int64_t m = 0; m < p->nsteps; ++m) {
+            euler_stage(p, a, a, h, hlam, &c);   /* predictor: Q^{m+1/2} */
+            euler_stage(p, h, a, b, lam, &c);    /* final: Q^{m+1} */
+            double *t = a; a = b; b = t;
+        }
+    }
+    double t1 = now_s();
+    if (seconds) *seconds = t1 - t0;
+
+    if (a != state) {               /* odd number of swaps: result lives in the scratch buffer */
+        memcpy(state, a, bytes);
+        b = a;                      /* free the scratch buffer, never the caller's array */
+    }
+    free(b);
+    free(h);
+    return 0;
+}
+
+int oracle_solve(const oracle_problem *p, double *state, int nthreads)
+{
+    return oracle_solve_timed(p, state, nthreads, 0);
+}
+
+void oracle_euler_flux(const double cells[4][3], double gamma, int limiter, double flux[3])
+{
+    euler_consts c;
+    c.gm1 = gamma - 1.0;
+    c.gamma = gamma;
+    c.limiter = limiter;
+    interface_flux(cells[0], cells[1], cells[2], cells[3], &c, flux);
+}
