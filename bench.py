@@ -1,0 +1,199 @@
+#!/usr/bin/env python3
+"""Benchmark: FP64 point-updates/s of the swept decomposition on one MI355X.
+
+One step = one swept solve of the heat equation (FTCS) and one of the
+Kuramoto-Sivashinsky equation (central differences + RK2), each on N = 2^20
+periodic points for 50,000 timesteps, initial states resident in HBM.  value =
+2 * N * 50,000 / (seconds per step).  The same line reports the classic
+decomposition (one launch per sub-step; replayed HIP graphs and plain stream
+launches), the live roofline figure of the dominant kernel (the swept Diamond
+kernel, timed with HIP events on its own stream) and the CPU oracle timed on
+the host's cores on a bounded sample.
+
+    python bench.py [--gpus 1] [--steps 3] [--warmup 1]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import workloads as W  # noqa: E402
+
+LOG2N = 20
+NSTEPS = 50_000
+METRIC = "FP64 point-updates/s (swept vs classic, 1 GPU) + batched p50/p99 solve latency"
+PEAK_FP64_TFLOPS = 78.6   # MI355X published FP64 vector peak
+PEAK_HBM_GBS = 8000.0
+# Algorithmic FP64 operations per point per sub-step level (add/sub/mul/neg-free),
+# as written in the canonical update rules.
+FLOPS_PER_POINT_LEVEL = {W.HEAT: 4, W.KS: 18}
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def timed_solves(plans, states, kind, reps, torch):
+    """Mean seconds of `reps` rounds of solving every (plan, state) pair."""
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        for plan, st in zip(plans, states):
+            getattr(plan, kind)(st)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / reps
+
+
+def cpu_baseline(budget_s: float = 12.0):
+    import oracle
+    oracle.build(force=False)
+    cores = oracle.threads(0)
+    n = 1 << LOG2N
+    samples = []
+    total_upd, total_s = 0, 0.0
+    for scheme in (W.HEAT, W.KS):
+        prob, ic = W.cfg_sweep(scheme, LOG2N)
+        probe = 20 if scheme == W.HEAT else 10
+        _, s = oracle.solve(prob.with_steps(probe), ic, timed=True)
+        steps = max(probe, int((budget_s / 2) / max(s / probe, 1e-9)))
+        steps = min(steps, NSTEPS)
+        _, s = oracle.solve(prob.with_steps(steps), ic, timed=True)
+        total_upd += n * steps
+        total_s += s
+        samples.append(f"{W.SCHEME_NAMES[scheme]} N=2^{LOG2N} x {steps} steps ({s:.1f} s)")
+    return {"value": total_upd / total_s, "unit": "point-updates/s", "cores": cores,
+            "kind": "oracle", "sample": "; ".join(samples) + f" of the {NSTEPS}-step workload"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--profile-reps", type=int, default=30)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); every box here has one "
+              "GPU and nothing in this build uses a second.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1705_03162_amd as sw
+
+    dev = torch.device("cuda:0")
+    n = 1 << LOG2N
+    probs, ics = [], []
+    for scheme in (W.HEAT, W.KS):
+        p, ic = W.cfg_sweep(scheme, LOG2N, NSTEPS)
+        probs.append(p)
+        ics.append(ic)
+    plans = [sw.Plan(p) for p in probs]
+    infos = [pl.info() for pl in plans]
+    for p, i in zip(probs, infos):
+        log(f"plan {W.SCHEME_NAMES[p.scheme]}: w={i['width']} T={i['threads']} P={i['points_per_lane']} "
+            f"H={i['levels_per_phase']} Q={i['full_phases']} rem={i['remainder']} "
+            f"launches swept={i['swept_launches']} classic={i['classic_launches']}")
+    fresh = lambda ic: torch.tensor(ic, dtype=torch.float64, device=dev)
+    states = [fresh(ic) for ic in ics]
+
+    # ---- swept: warmup + timed steps (each step starts again from the initial state,
+    # copied device-to-device outside the timed region)
+    init = [fresh(ic) for ic in ics]
+    for _ in range(args.warmup):
+        for st, i0 in zip(states, init):
+            st.copy_(i0)
+        timed_solves(plans, states, "swept", 1, torch)
+    step_times = []
+    for _ in range(args.steps):
+        for st, i0 in zip(states, init):
+            st.copy_(i0)
+        torch.cuda.synchronize()
+        step_times.append(timed_solves(plans, states, "swept", 1, torch))
+    swept_out = [st.cpu().numpy() for st in states]
+    t_step = float(np.mean(step_times))
+    updates = 2 * n * NSTEPS
+    value = updates / t_step
+    log(f"swept: {t_step * 1e3:.2f} ms/step -> {value:.3e} point-updates/s")
+
+    # per-scheme swept rates (one solve each)
+    per_scheme = {}
+    for p, pl, st, i0 in zip(probs, plans, states, init):
+        st.copy_(i0)
+        s = timed_solves([pl], [st], "swept", 1, torch)
+        per_scheme[W.SCHEME_NAMES[p.scheme]] = {"swept_s": s, "swept": n * NSTEPS / s}
+
+    # ---- classic: graph replays and stream launches
+    classic = {}
+    for flags, label in ((0, "graph"), (sw.SW_TUNE_NO_GRAPH, "stream")):
+        cp = [sw.Plan(p, flags=flags) for p in probs]
+        tot = 0.0
+        outs = []
+        for p, pl, i0 in zip(probs, cp, init):
+            st = i0.clone()
+            pl.classic(st)            # warm (graph capture)
+            st.copy_(i0)
+            s = timed_solves([pl], [st], "classic", 1, torch)
+            tot += s
+            outs.append(st.cpu().numpy())
+            per_scheme[W.SCHEME_NAMES[p.scheme]][f"classic_{label}"] = n * NSTEPS / s
+        classic[label] = updates / tot
+        if label == "graph":
+            bitwise = all(np.array_equal(a, b) for a, b in zip(swept_out, outs))
+        for pl in cp:
+            pl.close()
+        log(f"classic ({label}): {tot * 1e3:.2f} ms/step -> {classic[label]:.3e} point-updates/s")
+
+    # ---- roofline of the dominant kernel (swept Diamond), timed with HIP events
+    kern = []
+    for p, pl, i0, info in zip(probs, plans, init, infos):
+        scratch = i0.clone()
+        pl.swept(scratch)
+        us = pl.profile_phase(scratch, kind=1, reps=args.profile_reps)
+        launches = info["swept_launches"] - 3
+        flops = n * info["levels_per_phase"] * FLOPS_PER_POINT_LEVEL[p.scheme]
+        kern.append({"scheme": W.SCHEME_NAMES[p.scheme], "avg_us": us, "flops_per_launch": flops,
+                     "launches_per_solve": launches, "share_s": us * 1e-6 * launches})
+        log(f"diamond {W.SCHEME_NAMES[p.scheme]}: {us:.1f} us/launch, {flops / us * 1e-6:.2f} TFLOP/s")
+    dom = max(kern, key=lambda k: k["share_s"])
+    achieved = dom["flops_per_launch"] / (dom["avg_us"] * 1e-6) / 1e12
+    roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+                "kernel": f"swept_tile<{dom['scheme']}> diamond", "avg_us": dom["avg_us"],
+                "flops_per_launch": dom["flops_per_launch"]}
+
+    result = {
+        "metric": METRIC, "value": value, "unit": "point-updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": t_step * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"heat FTCS + Kuramoto-Sivashinsky RK2, periodic, N=2^{LOG2N}, "
+                               f"{NSTEPS} steps each, one swept solve per scheme per step",
+                   "n": n, "nsteps": NSTEPS,
+                   "tiles": {W.SCHEME_NAMES[p.scheme]: {"width": i["width"], "threads": i["threads"]}
+                             for p, i in zip(probs, infos)}},
+        "classic": {"graph": classic["graph"], "stream": classic["stream"],
+                    "speedup_swept_vs_graph": value / classic["graph"],
+                    "speedup_swept_vs_stream": value / classic["stream"]},
+        "per_scheme": per_scheme,
+        "swept_equals_classic_bitwise": bool(bitwise),
+        "roofline": roofline,
+    }
+    for pl in plans:
+        pl.close()
+    if not args.no_cpu:
+        log("cpu baseline (oracle) ...")
+        result["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,171 @@
+// Per-point update rules of the three schemes, in one fixed binary64 operation
+// order (no FMA contraction: every file is compiled with -ffp-contract=off).
+//
+// Each rule works on a lane-local run of P consecutive points: `ext` holds the
+// source level on those points plus R halo points on each side, `dst` holds
+// the destination row (which, for a final RK2 stage, still carries u^m / Q^m
+// at the same points).  Only points k in [klo, khi) are written; the others keep
+// their previous contents, which is what lets a tile keep its edges in place.
+//
+//   Heat  (Appendix B, Eq. Heatdisc):  T' = Fo (T_{i+1} + T_{i-1}) + (1 - 2 Fo) T_i
+//   KS    (Appendix C, Eqs. KSDisc, RKm, RKf): 5-point central differences,
+//         predictor u + dt/2 f(u), final u + dt f(u^{m+1/2})
+//   Euler (Appendix D): pressure-ratio limited reconstruction, Roe-averaged
+//         spectral radius, interface flux, same RK2 stages
+#pragma once
+
+#include <stdint.h>
+
+#if defined(__HIPCC__)
+#include <hip/hip_runtime.h>
+#define SW_HD __host__ __device__ inline
+#else
+#include <cmath>
+#define SW_HD inline
+#endif
+
+namespace sw {
+
+// Canonical constants, computed once on the host in the order written here and
+// passed by value to every kernel.
+struct Consts {
+    double fo, c0;                  // heat: Fo = (alpha*dt)/(dx*dx), 1 - 2 Fo
+    double c1, c2, c4, hdt, dt;     // KS: 1/(4 dx), 1/dx^2, c2*c2, dt/2, dt
+    double gm1, gamma, lam, hlam;   // Euler: gamma-1, gamma, dt/dx, lam/2
+    int32_t limiter, pad;           // Euler: 0 ratio as printed, 1 reciprocal
+    double ghost_l[3], ghost_r[3];  // Dirichlet ghost values per variable
+};
+
+SW_HD double sw_min(double a, double b) { return a < b ? a : b; }
+SW_HD double sw_sqrt(double x) { return sqrt(x); }
+SW_HD double sw_fabs(double x) { return fabs(x); }
+
+struct Heat {
+    static constexpr int R = 1, S = 1, NV = 1;
+    template <int P>
+    SW_HD static void level(double (&dst)[NV][P], const double (&ext)[NV][P + 2 * R],
+                            bool /*predictor*/, const Consts &c, int klo, int khi)
+    {
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            double s = ext[0][k + 2] + ext[0][k];
+            double v = c.fo * s + c.c0 * ext[0][k + 1];
+            if (k >= klo && k < khi) dst[0][k] = v;
+        }
+    }
+};
+
+struct KS {
+    static constexpr int R = 2, S = 2, NV = 1;
+    // f_i(v) = -((v_{i+1}^2 - v_{i-1}^2)/(4dx) + (v_{i+1} + v_{i-1} - 2v_i)/dx^2
+    //           + (v_{i+2} + v_{i-2} - 4(v_{i+1} + v_{i-1}) + 6v_i)/dx^4)
+    SW_HD static double rhs(double vm2, double vm1, double v0, double vp1, double vp2,
+                            const Consts &c)
+    {
+        double advect = (vp1 * vp1 - vm1 * vm1) * c.c1;
+        double diff2 = ((vp1 + vm1) - 2.0 * v0) * c.c2;
+        double diff4 = (((vp2 + vm2) - 4.0 * (vp1 + vm1)) + 6.0 * v0) * c.c4;
+        return -((advect + diff2) + diff4);
+    }
+    template <int P>
+    SW_HD static void level(double (&dst)[NV][P], const double (&ext)[NV][P + 2 * R],
+                            bool predictor, const Consts &c, int klo, int khi)
+    {
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            double f = rhs(ext[0][k], ext[0][k + 1], ext[0][k + 2], ext[0][k + 3], ext[0][k + 4], c);
+            double v = predictor ? ext[0][k + 2] + c.hdt * f : dst[0][k] + c.dt * f;
+            if (k >= klo && k < khi) dst[0][k] = v;
+        }
+    }
+};
+
+struct Euler {
+    static constexpr int R = 2, S = 2, NV = 3;
+
+    // Eq. EulerP with E the total energy per volume: P = (gamma-1)(E - (m u)/2), u = m/rho.
+    SW_HD static double pressure(double rho, double m, double e, const Consts &c)
+    {
+        double u = m / rho;
+        return c.gm1 * (e - 0.5 * (m * u));
+    }
+
+    // Flux through the interface between cells b and c, given cells a, b, c, d and
+    // their pressures.
+    SW_HD static void flux(const double qa[3], const double qb[3], const double qc[3],
+                           const double qd[3], double pa, double pb, double pc, double pd,
+                           const Consts &k, double out[3])
+    {
+        (void)qa; (void)qd;
+        // Eq. Pratio at b and c.
+        double pr_b = (pc - pb) / (pb - pa);
+        double pr_c = (pd - pc) / (pc - pb);
+        // Eqs. limitleft / limitright (tl: ratio used on the left state, tr: right).
+        double tl = k.limiter ? 1.0 / pr_b : pr_b;
+        double tr = k.limiter ? pr_c : 1.0 / pr_c;
+        bool okl = tl > 0.0 && tl < INFINITY;
+        bool okr = tr > 0.0 && tr < INFINITY;
+        double sl = 0.5 * sw_min(tl, 1.0), sr = 0.5 * sw_min(tr, 1.0);
+        double ql[3], qr[3];
+#pragma unroll
+        for (int v = 0; v < 3; ++v) {
+            ql[v] = okl ? qb[v] + sl * (qc[v] - qb[v]) : qb[v];
+            qr[v] = okr ? qc[v] + sr * (qb[v] - qc[v]) : qc[v];
+        }
+        // Eq. EulerF on both reconstructed states.
+        double ul = ql[1] / ql[0], ur = qr[1] / qr[0];
+        double pl = k.gm1 * (ql[2] - 0.5 * (ql[1] * ul));
+        double prr = k.gm1 * (qr[2] - 0.5 * (qr[1] * ur));
+        double fl[3] = {ql[1], ql[1] * ul + pl, ul * (ql[2] + pl)};
+        double fr[3] = {qr[1], qr[1] * ur + prr, ur * (qr[2] + prr)};
+        // Roe average and spectral radius.
+        double sql = sw_sqrt(ql[0]), sqr = sw_sqrt(qr[0]);
+        double rho_s = sw_sqrt(ql[0] * qr[0]);
+        double den = sql + sqr;
+        double u_s = (sql * ul + sqr * ur) / den;
+        double e_s = (sql * ql[2] + sqr * qr[2]) / den;
+        double p_s = k.gm1 * (e_s - 0.5 * ((rho_s * u_s) * u_s));
+        double r_sp = sw_sqrt((k.gamma * p_s) / rho_s) + sw_fabs(u_s);
+#pragma unroll
+        for (int v = 0; v < 3; ++v)
+            out[v] = 0.5 * ((fr[v] + fl[v]) + r_sp * (ql[v] - qr[v]));
+    }
+
+    template <int P>
+    SW_HD static void level(double (&dst)[NV][P], const double (&ext)[NV][P + 2 * R],
+                            bool predictor, const Consts &c, int klo, int khi)
+    {
+        double pres[P + 2 * R];
+#pragma unroll
+        for (int j = 0; j < P + 2 * R; ++j) pres[j] = pressure(ext[0][j], ext[1][j], ext[2][j], c);
+        const double coef = predictor ? c.hlam : c.lam;
+        // Interface j sits between ext cells j+1 and j+2 (point k has interfaces k, k+1).
+        double fprev[3];
+        {
+            double qa[3] = {ext[0][0], ext[1][0], ext[2][0]};
+            double qb[3] = {ext[0][1], ext[1][1], ext[2][1]};
+            double qc[3] = {ext[0][2], ext[1][2], ext[2][2]};
+            double qd[3] = {ext[0][3], ext[1][3], ext[2][3]};
+            flux(qa, qb, qc, qd, pres[0], pres[1], pres[2], pres[3], c, fprev);
+        }
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            double fnext[3];
+            double qa[3] = {ext[0][k + 1], ext[1][k + 1], ext[2][k + 1]};
+            double qb[3] = {ext[0][k + 2], ext[1][k + 2], ext[2][k + 2]};
+            double qc[3] = {ext[0][k + 3], ext[1][k + 3], ext[2][k + 3]};
+            double qd[3] = {ext[0][k + 4], ext[1][k + 4], ext[2][k + 4]};
+            flux(qa, qb, qc, qd, pres[k + 1], pres[k + 2], pres[k + 3], pres[k + 4], c, fnext);
+            const bool in = k >= klo && k < khi;
+#pragma unroll
+            for (int v = 0; v < 3; ++v) {
+                double base = predictor ? ext[v][k + 2] : dst[v][k];
+                double val = base + coef * (fprev[v] - fnext[v]);
+                if (in) dst[v][k] = val;
+                fprev[v] = fnext[v];
+            }
+        }
+    }
+};
+
+}  // namespace sw

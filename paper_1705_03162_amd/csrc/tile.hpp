@@ -1,0 +1,214 @@
+// Geometry of one swept tile: which points a lane owns, where its two working
+// rows come from and go to, and which points each level computes.
+//
+// Swept rule on a 1D grid (Sec. 3.2, Fig. 1 and 2; Sec. 3.3 for two sub-steps):
+// a node of w points advances every level its domain of dependence allows.  A
+// stencil of radius r shrinks the computable set by r per side per level, so an
+// Up triangle computes levels 1..H-1 on [r s, w - r s) with H = w / (2 r).  The
+// two edges it cannot finish travel to the neighbours; the next launch, offset
+// by w/2, fills the gap between two triangles (a Diamond: widening for H levels,
+// narrowing for H-1 more), and a final Down triangle completes a full level.
+//
+// Working array (Sec. 3.2): two rows, row 0 for even and row 1 for odd levels,
+// overwritten in place; the edges left behind in the rows are exactly the values
+// the neighbour needs.  Here the two rows of a tile live in registers: lane g of
+// the work-group owns the P consecutive points [g P, g P + P) of both rows.
+//
+// Edge slots: the edge buffer holds 2K slots, each two rows of E = w/2 + r
+// points per variable, stored [var][row][e].  An "L" slot holds tile points
+// [0, w/2 + r) of a node, an "R" slot its points [w/2 - r, w); the r points
+// around the middle (the triangle tip) appear in both, as the paper copies the
+// tips into both edge arrays.  In a phase with offset o (0, or 1 for w/2), tile
+// j reads slot a = 2j + o (an R slot: its points [-r, w/2)) and slot
+// b = 2j + o + 1 (an L slot: its points [w/2, w + r)), and writes its own L and R
+// slots back into a and b: each slot is read and rewritten by exactly one tile
+// per launch (the L/R swap of Sec. 3.2).
+//
+// Relative levels start at an even absolute level in every phase (H is even), so
+// odd relative levels are the odd absolute levels: predictors for RK2 schemes.
+#pragma once
+
+#include "schemes.hpp"
+
+namespace sw {
+
+enum PhaseKind : int32_t { PH_UP = 0, PH_DIAMOND = 1, PH_DOWN = 2 };
+
+// Largest work-group for which a tile kernel is compiled: the two rows take
+// 2*nv*P doubles per lane, and the register file must hold them for every wave.
+constexpr int max_threads_for(int nv, int P) { return nv > 1 ? 256 : (P >= 16 ? 512 : 1024); }
+
+struct TileArgs {
+    double *state;     // [nv][n]
+    double *edges;     // 2K slots of nv*2*E doubles
+    int64_t n;         // grid points
+    int64_t K;         // tiles per phase (n / w)
+    int32_t w;         // tile width
+    int32_t H;         // w / (2 r)
+    int32_t E;         // w/2 + r
+    int32_t kind;      // PhaseKind
+    int32_t levels;    // Up/Down: levels to advance (<= H); Diamond: ignored (2H - 1)
+    int32_t offset;    // 0, or 1 for tiles shifted by w/2
+    int32_t dirichlet; // 1: the tile straddling the domain end sees ghost values
+    int32_t pad;
+    Consts c;
+};
+
+SW_HD int64_t tile_start(const TileArgs &a, int64_t j) { return j * a.w + (a.offset ? a.w / 2 : 0); }
+SW_HD int64_t wrap_once(int64_t x, int64_t n) { return x >= n ? x - n : x; }
+SW_HD int64_t slot_a(const TileArgs &a, int64_t j)
+{
+    int64_t s = 2 * j + a.offset;
+    return s >= 2 * a.K ? s - 2 * a.K : s;
+}
+SW_HD int64_t slot_b(const TileArgs &a, int64_t j)
+{
+    int64_t s = 2 * j + a.offset + 1;
+    return s >= 2 * a.K ? s - 2 * a.K : s;
+}
+template <class Sch>
+SW_HD int64_t slot_base(const TileArgs &a, int64_t s) { return s * (int64_t)Sch::NV * 2 * a.E; }
+
+// Number of levels a tile computes in this launch.
+SW_HD int tile_levels(const TileArgs &a)
+{
+    if (a.kind == PH_UP) return a.levels < a.H ? a.levels : a.H - 1;
+    if (a.kind == PH_DIAMOND) return 2 * a.H - 1;
+    return a.levels;
+}
+
+// Half-width (in units of r) of the set of points computed at relative level s;
+// the set is [w/2 - r m, w/2 + r m).
+SW_HD int half_width(const TileArgs &a, int s)
+{
+    if (a.kind == PH_UP) return a.H - s;
+    if (a.kind == PH_DOWN) return s;
+    return s < 2 * a.H - s ? s : 2 * a.H - s;
+}
+
+// With Dirichlet ends, the tile of an offset phase that wraps past the end of
+// the grid has the wall at its centre: left half = the last w/2 points, right
+// half = the first w/2 points, each seeing ghost values across the wall.
+SW_HD bool straddles_wall(const TileArgs &a, int64_t j)
+{
+    return a.dirichlet && a.offset == 1 && j == a.K - 1;
+}
+
+// Load lane g's rows.  Up: row 0 = the current full level from the state.
+// Diamond/Down: both rows from the two source slots, plus the r points just
+// outside the tile on each side (row 1: the previous triangles' tips, read once
+// at the widest level).
+template <class Sch, int P>
+SW_HD void lane_load(const TileArgs &a, int64_t j, int g, double (&r0)[Sch::NV][P],
+                     double (&r1)[Sch::NV][P], double (&hl)[Sch::NV][Sch::R],
+                     double (&hr)[Sch::NV][Sch::R])
+{
+    constexpr int NV = Sch::NV, R = Sch::R;
+    const int half = a.w / 2;
+    const int x0 = g * P;
+    if (a.kind == PH_UP) {
+        const int64_t g0 = tile_start(a, j);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+#pragma unroll
+            for (int k = 0; k < P; ++k) {
+                r0[v][k] = a.state[(int64_t)v * a.n + g0 + x0 + k];
+                r1[v][k] = 0.0;
+            }
+#pragma unroll
+            for (int i = 0; i < R; ++i) { hl[v][i] = 0.0; hr[v][i] = 0.0; }
+        }
+        return;
+    }
+    const double *sa = a.edges + slot_base<Sch>(a, slot_a(a, j));
+    const double *sb = a.edges + slot_base<Sch>(a, slot_b(a, j));
+    const bool left = x0 < half;
+    const double *src = left ? sa : sb;
+    const int e0 = left ? x0 + R : x0 - half;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            r0[v][k] = src[(v * 2 + 0) * a.E + e0 + k];
+            r1[v][k] = src[(v * 2 + 1) * a.E + e0 + k];
+        }
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            hl[v][i] = sa[(v * 2 + 1) * a.E + i];
+            hr[v][i] = sb[(v * 2 + 1) * a.E + half + i];
+        }
+    }
+    // Dirichlet: in unshifted phases the first tile starts at the left wall and
+    // the last ends at the right wall, so the points beyond them are ghosts.
+    if (a.dirichlet && a.offset == 0) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+#pragma unroll
+            for (int i = 0; i < R; ++i) {
+                if (j == 0) hl[v][i] = a.c.ghost_l[v];
+                if (j == a.K - 1) hr[v][i] = a.c.ghost_r[v];
+            }
+        }
+    }
+}
+
+// Store lane g's rows: Up and Diamond write the new L slot (into a) and R slot
+// (into b); an Up that stops below the triangle tip, and every Down, also write
+// their top level's computed points to the state.
+template <class Sch, int P>
+SW_HD void lane_store(const TileArgs &a, int64_t j, int g, const double (&r0)[Sch::NV][P],
+                      const double (&r1)[Sch::NV][P])
+{
+    constexpr int NV = Sch::NV, R = Sch::R;
+    const int half = a.w / 2;
+    const int x0 = g * P;
+    if (a.kind != PH_DOWN) {
+        double *sa = a.edges + slot_base<Sch>(a, slot_a(a, j));
+        double *sb = a.edges + slot_base<Sch>(a, slot_b(a, j));
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+#pragma unroll
+            for (int k = 0; k < P; ++k) {
+                const int x = x0 + k;
+                if (x < half + R) {
+                    sa[(v * 2 + 0) * a.E + x] = r0[v][k];
+                    sa[(v * 2 + 1) * a.E + x] = r1[v][k];
+                }
+                if (x >= half - R) {
+                    sb[(v * 2 + 0) * a.E + x - (half - R)] = r0[v][k];
+                    sb[(v * 2 + 1) * a.E + x - (half - R)] = r1[v][k];
+                }
+            }
+        }
+    }
+    int top = -1;
+    if (a.kind == PH_DOWN) top = a.levels;
+    else if (a.kind == PH_UP && a.levels < a.H) top = a.levels;
+    if (top < 0) return;
+    const int m = a.kind == PH_DOWN ? top : a.H - top;
+    const int lo = half - R * m, hi = half + R * m;
+    const int64_t g0 = tile_start(a, j);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            const int x = x0 + k;
+            if (x >= lo && x < hi) {
+                const double val = (top & 1) ? r1[v][k] : r0[v][k];
+                a.state[(int64_t)v * a.n + wrap_once(g0 + x, a.n)] = val;
+            }
+        }
+    }
+}
+
+// Lane-local bounds [klo, khi) of the points computed at relative level s.
+SW_HD void lane_bounds(const TileArgs &a, int s, int g, int P, int R, int &klo, int &khi)
+{
+    const int m = half_width(a, s);
+    const int half = a.w / 2;
+    int lo = half - R * m - g * P, hi = half + R * m - g * P;
+    klo = lo < 0 ? 0 : (lo > P ? P : lo);
+    khi = hi < 0 ? 0 : (hi > P ? P : hi);
+}
+
+}  // namespace sw

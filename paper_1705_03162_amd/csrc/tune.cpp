@@ -1,0 +1,67 @@
+#include "tune.hpp"
+
+#include <dlfcn.h>
+
+#include <cstdio>
+#include <cstdlib>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+
+#include "plan_core.hpp"
+
+namespace sw {
+
+namespace {
+
+std::once_flag g_once;
+std::map<std::pair<int, int>, std::pair<int, int>> g_table;
+
+std::string table_path()
+{
+    if (const char *env = std::getenv("SWEPT_TUNE_FILE")) return env;
+    Dl_info info;
+    if (dladdr((void *)&tuned_shape, &info) && info.dli_fname) {
+        std::string lib = info.dli_fname;
+        size_t slash = lib.rfind('/');
+        std::string dir = slash == std::string::npos ? "." : lib.substr(0, slash);
+        return dir + "/tune_gfx950.txt";
+    }
+    return "tune_gfx950.txt";
+}
+
+void load()
+{
+    FILE *f = std::fopen(table_path().c_str(), "r");
+    if (!f) return;
+    char line[256];
+    while (std::fgets(line, sizeof line, f)) {
+        if (line[0] == '#') continue;
+        int scheme, lg, width, threads;
+        if (std::sscanf(line, "%d %d %d %d", &scheme, &lg, &width, &threads) == 4)
+            g_table[{scheme, lg}] = {width, threads};
+    }
+    std::fclose(f);
+}
+
+}  // namespace
+
+bool tuned_shape(const sw_problem &p, int *width, int *threads)
+{
+    std::call_once(g_once, load);
+    int lg = 0;
+    while (lg < 62 && ((int64_t)1 << (lg + 1)) <= p.n) ++lg;
+    auto it = g_table.find({p.scheme, lg});
+    if (it == g_table.end()) return false;
+    const int w = it->second.first, t = it->second.second;
+    if (w <= 0 || t <= 0 || p.n % w != 0) return false;
+    Geom g;
+    std::string err;
+    if (make_geom(p, w, t, &g, &err) != 0) return false;
+    *width = w;
+    *threads = t;
+    return true;
+}
+
+}  // namespace sw

@@ -1,0 +1,173 @@
+"""The C interface on the CPU: the library loads, exports every symbol declared
+in include/swept.h, and its host logic (validation, plan geometry, error
+reporting) works without a GPU.  No kernel is launched here."""
+import ctypes
+import json
+import os
+import re
+
+import pytest
+
+import workloads as W
+from paper_1705_03162_amd import _native as N
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "swept.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*([a-z_0-9]+)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(N.LIB_PATH):
+        from paper_1705_03162_amd import build
+        build.build(verbose=False)
+    return N.lib()
+
+
+def test_header_declares_the_interface():
+    names = declared_functions()
+    for n in ["swept_plan", "swept_plan_info", "swept_solve", "classic_solve", "swept_plan_destroy",
+              "batch_create", "batch_submit", "batch_run", "batch_poll", "batch_wait",
+              "batch_cancel", "batch_destroy", "sw_strerror", "sw_last_error"]:
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    raw = ctypes.CDLL(N.LIB_PATH)
+    for name in declared_functions():
+        assert hasattr(raw, name), name
+    assert set(declared_functions()) <= set(N.SIGNATURES)
+
+
+def _plan(lib, prob, width=0, threads=0, flags=0):
+    p = N.problem_struct(prob)
+    t = N.SwTuning(width, threads, flags)
+    h = ctypes.c_void_p()
+    rc = lib.swept_plan(ctypes.byref(p), ctypes.byref(t), ctypes.byref(h))
+    return rc, h
+
+
+def _info(lib, h):
+    i = N.SwPlanInfo()
+    assert lib.swept_plan_info(h, ctypes.byref(i)) == 0
+    return i
+
+
+def test_plan_geometry_heat_cfg1(lib):
+    prob, _ = W.cfg_heat_small()
+    rc, h = _plan(lib, prob, 64, 64)
+    assert rc == 0
+    i = _info(lib, h)
+    assert (i.width, i.threads, i.points_per_lane, i.radius, i.substeps, i.nvars) == (64, 64, 1, 1, 1, 1)
+    assert (i.nodes, i.levels_per_phase, i.full_phases, i.remainder) == (16, 32, 312, 16)
+    assert i.swept_launches == 1 + 311 + 1 + 2 and i.classic_launches == 10_000
+    lib.swept_plan_destroy(h)
+
+
+def test_plan_geometry_ks_large(lib):
+    rc, h = _plan(lib, W.ks_problem(1 << 20, 50_000), 1024, 128)
+    assert rc == 0
+    i = _info(lib, h)
+    assert (i.points_per_lane, i.levels_per_phase, i.full_phases, i.remainder) == (8, 256, 390, 160)
+    assert i.nodes == 1024 and i.classic_launches == 100_000 and i.swept_launches == 393
+    lib.swept_plan_destroy(h)
+
+
+GOLDEN = json.load(open(os.path.join(ROOT, "tests", "golden", "paper_geometry.json")))
+
+
+def _phase_levels(width, radius):
+    """Levels per swept phase for a node of `width` points: H = w / (2 r)."""
+    return width // (2 * radius)
+
+
+def test_paper_geometry_pins():
+    """Printed geometry of Sec. 3.2 and Sec. 5 follows from H = w/(2r) and two rows of
+    w + k - 1 values (k = 2r + 1)."""
+    n = 512
+    assert sum(2 * j for j in range(1, n // 2 + 1)) == GOLDEN["full_triangle_values_n512_radius1"]["value"]
+    assert 2 * (n + 3 - 1) == GOLDEN["two_row_working_array_values_n512_width3"]["value"]
+    w32 = GOLDEN["register_ks_node_points"]["value"]
+    h32 = _phase_levels(w32, 2)                      # KS: r = 2, two sub-steps per step
+    assert h32 // 2 == GOLDEN["register_ks_timesteps_per_cycle"]["value"]
+    assert h32 == GOLDEN["register_ks_launch_ratio_vs_classic"]["value"]
+    assert _phase_levels(128, 2) // h32 == GOLDEN["shared_n128_vs_register_n32_launch_ratio"]["value"]
+
+
+@pytest.mark.parametrize("width,threads", [(128, 64), (256, 64), (1024, 128)])
+def test_plan_levels_per_phase_matches_formula(lib, width, threads):
+    rc, h = _plan(lib, W.ks_problem(1 << 14, 1000), width, threads)
+    assert rc == 0
+    i = _info(lib, h)
+    assert i.levels_per_phase == _phase_levels(width, 2)
+    # one phase advances H levels = H/2 timesteps; classic takes 2 launches per timestep
+    assert i.full_phases == (2 * 1000) // i.levels_per_phase
+    lib.swept_plan_destroy(h)
+
+
+def test_default_shape_divides_n(lib):
+    for prob in (W.heat_problem(1 << 20, 10), W.ks_problem(1 << 16, 10), W.sod_problem(1 << 14, 10),
+                 W.heat_problem(1024, 10), W.ks_problem(3 * 1024, 5)):
+        rc, h = _plan(lib, prob)
+        assert rc == 0
+        i = _info(lib, h)
+        assert i.swept_ok == 1 and prob.n % i.width == 0
+        lib.swept_plan_destroy(h)
+
+
+def test_no_legal_width_still_plans_for_classic(lib):
+    rc, h = _plan(lib, W.heat_problem(1000, 10))
+    assert rc == 0
+    assert _info(lib, h).swept_ok == 0
+    lib.swept_plan_destroy(h)
+
+
+@pytest.mark.parametrize("mutate,code", [
+    (lambda p: setattr(p, "scheme", 7), N.SW_EINVAL),
+    (lambda p: setattr(p, "bc", 3), N.SW_EINVAL),
+    (lambda p: setattr(p, "n", 0), N.SW_EINVAL),
+    (lambda p: setattr(p, "nsteps", -1), N.SW_EINVAL),
+    (lambda p: setattr(p, "dt", 0.0), N.SW_EINVAL),
+    (lambda p: setattr(p, "dx", float("nan")), N.SW_EINVAL),
+    (lambda p: setattr(p, "flags", 8), N.SW_EINVAL),
+])
+def test_invalid_problems_rejected(lib, mutate, code):
+    p = N.problem_struct(W.heat_problem(256, 10))
+    mutate(p)
+    h = ctypes.c_void_p()
+    assert lib.swept_plan(ctypes.byref(p), None, ctypes.byref(h)) == code
+    assert not h.value
+    assert len(lib.sw_last_error()) > 0
+
+
+@pytest.mark.parametrize("width,threads", [(96, 64), (64, 32), (64 * 32, 64), (128, 128 + 64),
+                                           (256, 64 * 2)])
+def test_invalid_shapes_rejected(lib, width, threads):
+    rc, h = _plan(lib, W.ks_problem(1 << 12, 10), width, threads)
+    # KS needs >= 2 points per lane: (256, 128) has P = 2 and is legal
+    if (width, threads) == (256, 128):
+        assert rc == 0
+        lib.swept_plan_destroy(h)
+    else:
+        assert rc == N.SW_EINVAL
+
+
+def test_width_must_divide_n(lib):
+    rc, _ = _plan(lib, W.heat_problem(1000, 10), 64, 64)
+    assert rc == N.SW_EINVAL
+
+
+def test_strerror_strings(lib):
+    for code in (0, -1, -2, -3, -4, -5, -6, -7, 99):
+        assert lib.sw_strerror(code)
+
+
+def test_destroy_null_is_noop(lib):
+    lib.swept_plan_destroy(None)
+    lib.batch_destroy(None)
