@@ -73,6 +73,48 @@ def cpu_baseline(budget_s: float = 12.0):
             "kind": "oracle", "sample": "; ".join(samples) + f" of the {NSTEPS}-step workload"}
 
 
+def rate_of(sw, torch, prob, ic, kind, flags=0, reps=2):
+    """Best-of-reps point-updates/s of one solve (state resident, graph captured)."""
+    with sw.Plan(prob, flags=flags) as plan:
+        x0 = torch.tensor(ic, dtype=torch.float64, device="cuda")
+        x = x0.clone()
+        getattr(plan, kind)(x)
+        best = float("inf")
+        for _ in range(reps):
+            x.copy_(x0)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            getattr(plan, kind)(x)
+            torch.cuda.synchronize()
+            best = min(best, time.perf_counter() - t0)
+        info = plan.info()
+    return prob.n * prob.nsteps / best, best, info, x
+
+
+def suite_sweep(schemes, log2ns, max_steps):
+    """One JSON line per (scheme, N): swept vs classic (graph and stream launches)."""
+    import torch
+    import paper_1705_03162_amd as sw
+    for scheme in schemes:
+        for lg in log2ns:
+            if scheme == W.EULER:
+                prob, ic = W.cfg_sod(lg)
+            else:
+                prob, ic = W.cfg_sweep(scheme, lg)
+            full = prob.nsteps
+            prob = prob.with_steps(min(full, max_steps))
+            rs, ts, info, xs = rate_of(sw, torch, prob, ic, "swept")
+            rg, tg, _, xg = rate_of(sw, torch, prob, ic, "classic")
+            rst, tst, _, _ = rate_of(sw, torch, prob, ic, "classic", flags=sw.SW_TUNE_NO_GRAPH, reps=1)
+            same = bool(torch.equal(xs, xg))
+            print(json.dumps({"scheme": W.SCHEME_NAMES[scheme], "n": prob.n, "steps": prob.nsteps,
+                              "full_steps": full, "swept": rs, "classic_graph": rg,
+                              "classic_stream": rst, "swept_over_classic_graph": rs / rg,
+                              "swept_over_classic_stream": rs / rst, "swept_ms": ts * 1e3,
+                              "classic_graph_ms": tg * 1e3, "width": info["width"],
+                              "threads": info["threads"], "bitwise_equal": same}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -80,11 +122,18 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--profile-reps", type=int, default=30)
+    ap.add_argument("--suite", default="main", choices=["main", "sweep", "euler"],
+                    help="main: the one-line benchmark; sweep/euler: per-N swept vs classic lines")
+    ap.add_argument("--max-steps", type=int, default=20_000)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); every box here has one "
               "GPU and nothing in this build uses a second.", file=sys.stderr)
         sys.exit(2)
+    if args.suite != "main":
+        schemes = [W.EULER] if args.suite == "euler" else [W.HEAT, W.KS]
+        suite_sweep(schemes, range(12, 21), args.max_steps)
+        return
 
     import torch
     import paper_1705_03162_amd as sw

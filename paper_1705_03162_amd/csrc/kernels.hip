@@ -21,42 +21,34 @@ namespace {
 constexpr int DPP_WAVE_SHL1 = 0x130;  // lane i receives lane i+1
 constexpr int DPP_WAVE_SHR1 = 0x138;  // lane i receives lane i-1
 
-// Move a double across lanes with a DPP control; lanes whose source lane lies
-// outside the wave keep `old`.
+// Zero-filling DPP move: lanes whose source lies outside the wave read 0.
 template <int CTRL>
-__device__ __forceinline__ double dpp_move(double old, double v)
+__device__ __forceinline__ double dpp_zero(double v)
 {
-    const unsigned long long o = __builtin_bit_cast(unsigned long long, old);
     const unsigned long long x = __builtin_bit_cast(unsigned long long, v);
-    const int lo = __builtin_amdgcn_update_dpp((int)(unsigned)o, (int)(unsigned)x, CTRL, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp((int)(unsigned)(o >> 32), (int)(unsigned)(x >> 32), CTRL,
-                                               0xF, 0xF, false);
+    const int lo = __builtin_amdgcn_mov_dpp((int)(unsigned)x, CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(unsigned)(x >> 32), CTRL, 0xF, 0xF, true);
     const unsigned long long r = ((unsigned long long)(unsigned)hi << 32) | (unsigned long long)(unsigned)lo;
     return __builtin_bit_cast(double, r);
 }
 
-template <class Sch, int P, bool ODD>
-__device__ __forceinline__ void level_step(const TileArgs &a, int g, int NW, int s,
+// One level of a tile: gather the source row with halos, then update the points
+// of the computed set [w/2 - r m, w/2 + r m).  Element k of the wave's lanes is
+// inside for a contiguous range of lanes whose ends take only two values each
+// over k (their residues are compile-time), so a level needs four lane compares
+// however many points a lane holds.  A wave with no point inside skips the level
+// (after publishing its boundary values for its neighbours), which recovers most
+// of the idle half of a triangle in multi-wave tiles.
+template <class Sch, int P, bool ODD, bool MULTI, bool WALL, bool INC, int SMOD>
+__device__ __forceinline__ void level_step(const TileArgs &a, int g, int NW, int s, int m,
                                            const double (&src)[Sch::NV][P], double (&dst)[Sch::NV][P],
                                            const double (&hl)[Sch::NV][Sch::R],
-                                           const double (&hr)[Sch::NV][Sch::R], bool wall,
+                                           const double (&hr)[Sch::NV][Sch::R],
                                            double (*xch)[16][2][Sch::NV][Sch::R])
 {
     constexpr int NV = Sch::NV, R = Sch::R;
-    double ext[NV][P + 2 * R];
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
-#pragma unroll
-        for (int k = 0; k < P; ++k) ext[v][R + k] = src[v][k];
-#pragma unroll
-        for (int i = 0; i < R; ++i) {
-            // wave-edge lanes get the tile's outer halo; interior lanes their neighbour's points
-            ext[v][i] = dpp_move<DPP_WAVE_SHR1>(hl[v][i], src[v][P - R + i]);
-            ext[v][R + P + i] = dpp_move<DPP_WAVE_SHL1>(hr[v][i], src[v][i]);
-        }
-    }
-    if (NW > 1) {
-        const int lane = g & 63, wave = g >> 6, buf = s & 1;
+    const int lane = g & 63, wave = g >> 6, buf = s & 1;
+    if (MULTI) {
         if (lane == 0) {
 #pragma unroll
             for (int v = 0; v < NV; ++v)
@@ -70,6 +62,42 @@ __device__ __forceinline__ void level_step(const TileArgs &a, int g, int NW, int
                 for (int i = 0; i < R; ++i) xch[buf][wave][1][v][i] = src[v][P - R + i];
         }
         __syncthreads();
+    }
+    const int half = a.w >> 1;
+    const int lo = __builtin_amdgcn_readfirstlane(half - R * m);
+    const int hi = __builtin_amdgcn_readfirstlane(half + R * m);
+    const int base = __builtin_amdgcn_readfirstlane(g & ~63);  // first lane of this wave
+    int lmin, lmax;  // lanes of this wave holding at least one computed point: [lmin, lmax)
+    element_lane_span(P, R, INC, SMOD, lo, hi, base, lmin, lmax);
+    if (!(lmin < 64 && lmax > 0 && lmin < lmax)) return;
+
+    double ext[NV][P + 2 * R];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+#pragma unroll
+        for (int k = 0; k < P; ++k) ext[v][R + k] = src[v][k];
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+            ext[v][i] = dpp_zero<DPP_WAVE_SHR1>(src[v][P - R + i]);
+            ext[v][R + P + i] = dpp_zero<DPP_WAVE_SHL1>(src[v][i]);
+        }
+    }
+    // The tile's outer halo is read by the widest level of a Diamond/Down only.
+    if (s == a.H && a.kind != PH_UP) {
+        if (g == 0) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v)
+#pragma unroll
+                for (int i = 0; i < R; ++i) ext[v][i] = hl[v][i];
+        }
+        if (g == 64 * NW - 1) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v)
+#pragma unroll
+                for (int i = 0; i < R; ++i) ext[v][R + P + i] = hr[v][i];
+        }
+    }
+    if (MULTI) {
         if (lane == 0 && wave > 0) {
 #pragma unroll
             for (int v = 0; v < NV; ++v)
@@ -83,7 +111,7 @@ __device__ __forceinline__ void level_step(const TileArgs &a, int g, int NW, int
                 for (int i = 0; i < R; ++i) ext[v][R + P + i] = xch[buf][wave + 1][0][v][i];
         }
     }
-    if (wall) {
+    if (WALL) {
         const int gw = a.w / (2 * P) - 1;  // last lane left of the wall
         if (g == gw) {
 #pragma unroll
@@ -98,9 +126,72 @@ __device__ __forceinline__ void level_step(const TileArgs &a, int g, int NW, int
                 for (int i = 0; i < R; ++i) ext[v][i] = a.c.ghost_l[v];
         }
     }
-    int klo, khi;
-    lane_bounds(a, s, g, P, R, klo, khi);
-    Sch::template level<P>(dst, ext, ODD, a.c, klo, khi);
+    bool in[P];
+#pragma unroll
+    for (int k = 0; k < P; ++k) {
+        // la, lb take two values each over k: four distinct lane compares per level
+        int la, lb;
+        element_lane_bounds(P, R, INC, SMOD, lo, hi, base, k, la, lb);
+        in[k] = lane >= la && lane < lb;
+    }
+    Sch::template level<P>(dst, ext, ODD, a.c, in);
+}
+
+// Levels s0 + U, s0 + U + 1, ... of one aligned group (s0 = 1 mod G, so the
+// row parity and the residues of the computed set are compile-time).  m = s for
+// a widening segment, m = mtop - s for a narrowing one.
+template <class Sch, int P, bool MULTI, bool WALL, bool INC, int U, int G>
+__device__ __forceinline__ void run_group(const TileArgs &a, int g, int NW, int s0, int s_last, int mtop,
+                                          bool full, double (&r0)[Sch::NV][P], double (&r1)[Sch::NV][P],
+                                          const double (&hl)[Sch::NV][Sch::R],
+                                          const double (&hr)[Sch::NV][Sch::R],
+                                          double (*xch)[16][2][Sch::NV][Sch::R])
+{
+    if constexpr (U < G) {
+        const int s = s0 + U;
+        if (full || s <= s_last) {
+            const int m = INC ? s : mtop - s;
+            constexpr int SMOD = (1 + U) % G;
+            if constexpr (((1 + U) & 1) != 0)
+                level_step<Sch, P, true, MULTI, WALL, INC, SMOD>(a, g, NW, s, m, r0, r1, hl, hr, xch);
+            else
+                level_step<Sch, P, false, MULTI, WALL, INC, SMOD>(a, g, NW, s, m, r1, r0, hl, hr, xch);
+            run_group<Sch, P, MULTI, WALL, INC, U + 1, G>(a, g, NW, s0, s_last, mtop, full, r0, r1, hl, hr, xch);
+        }
+    }
+}
+
+// Levels [s_first, s_last] (s_first = 1 mod G) in full groups plus one partial group.
+template <class Sch, int P, bool MULTI, bool WALL, bool INC>
+__device__ __forceinline__ void run_segment(const TileArgs &a, int g, int NW, int s_first, int s_last,
+                                            int mtop, double (&r0)[Sch::NV][P], double (&r1)[Sch::NV][P],
+                                            const double (&hl)[Sch::NV][Sch::R],
+                                            const double (&hr)[Sch::NV][Sch::R],
+                                            double (*xch)[16][2][Sch::NV][Sch::R])
+{
+    constexpr int G = group_len(P, Sch::R);
+    int s0 = s_first;
+    for (; s0 + G - 1 <= s_last; s0 += G)
+        run_group<Sch, P, MULTI, WALL, INC, 0, G>(a, g, NW, s0, s_last, mtop, true, r0, r1, hl, hr, xch);
+    if (s0 <= s_last)
+        run_group<Sch, P, MULTI, WALL, INC, 0, G>(a, g, NW, s0, s_last, mtop, false, r0, r1, hl, hr, xch);
+}
+
+template <class Sch, int P, bool MULTI, bool WALL>
+__device__ __forceinline__ void run_levels(const TileArgs &a, int g, int NW, double (&r0)[Sch::NV][P],
+                                           double (&r1)[Sch::NV][P], const double (&hl)[Sch::NV][Sch::R],
+                                           const double (&hr)[Sch::NV][Sch::R],
+                                           double (*xch)[16][2][Sch::NV][Sch::R])
+{
+    const int nlev = tile_levels(a);
+    if (a.kind == PH_UP) {
+        run_segment<Sch, P, MULTI, WALL, false>(a, g, NW, 1, nlev, a.H, r0, r1, hl, hr, xch);
+    } else if (a.kind == PH_DOWN) {
+        run_segment<Sch, P, MULTI, WALL, true>(a, g, NW, 1, nlev, 0, r0, r1, hl, hr, xch);
+    } else {
+        run_segment<Sch, P, MULTI, WALL, true>(a, g, NW, 1, a.H, 0, r0, r1, hl, hr, xch);
+        run_segment<Sch, P, MULTI, WALL, false>(a, g, NW, a.H + 1, nlev, 2 * a.H, r0, r1, hl, hr, xch);
+    }
 }
 
 template <class Sch, int P, int MAXT>
@@ -113,15 +204,15 @@ __global__ __launch_bounds__(MAXT) void swept_tile(TileArgs a)
     const int64_t j = blockIdx.x;
     double r0[NV][P], r1[NV][P], hl[NV][R], hr[NV][R];
     lane_load<Sch, P>(a, j, g, r0, r1, hl, hr);
-    const int nlev = tile_levels(a);
     const bool wall = straddles_wall(a, j);
-    int s = 1;
-    for (; s + 1 <= nlev; s += 2) {
-        level_step<Sch, P, true>(a, g, NW, s, r0, r1, hl, hr, wall, xch);
-        level_step<Sch, P, false>(a, g, NW, s + 1, r1, r0, hl, hr, wall, xch);
+    if (NW > 1) {
+        if (wall) run_levels<Sch, P, true, true>(a, g, NW, r0, r1, hl, hr, xch);
+        else run_levels<Sch, P, true, false>(a, g, NW, r0, r1, hl, hr, xch);
+        __syncthreads();  // every wave has read its inputs before any slot is rewritten
+    } else {
+        if (wall) run_levels<Sch, P, false, true>(a, g, NW, r0, r1, hl, hr, xch);
+        else run_levels<Sch, P, false, false>(a, g, NW, r0, r1, hl, hr, xch);
     }
-    if (s <= nlev) level_step<Sch, P, true>(a, g, NW, s, r0, r1, hl, hr, wall, xch);
-    if (NW > 1) __syncthreads();  // every wave has read its inputs before any slot is rewritten
     lane_store<Sch, P>(a, j, g, r0, r1);
 }
 
@@ -153,7 +244,8 @@ __global__ __launch_bounds__(256) void classic_level(const double *__restrict__ 
     const bool in_place = Sch::S == 2 && !predictor;
 #pragma unroll
     for (int v = 0; v < NV; ++v) out[v][0] = in_place ? dst[(int64_t)v * n + i] : 0.0;
-    Sch::template level<1>(out, ext, predictor != 0, c, 0, 1);
+    const bool all[1] = {true};
+    Sch::template level<1>(out, ext, predictor != 0, c, all);
 #pragma unroll
     for (int v = 0; v < NV; ++v) dst[(int64_t)v * n + i] = out[v][0];
 }

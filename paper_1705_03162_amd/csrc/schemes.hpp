@@ -4,8 +4,8 @@
 // Each rule works on a lane-local run of P consecutive points: `ext` holds the
 // source level on those points plus R halo points on each side, `dst` holds
 // the destination row (which, for a final RK2 stage, still carries u^m / Q^m
-// at the same points).  Only points k in [klo, khi) are written; the others keep
-// their previous contents, which is what lets a tile keep its edges in place.
+// at the same points).  Only points k with in[k] set are written; the others
+// keep their previous contents, which is what lets a tile keep its edges in place.
 //
 //   Heat  (Appendix B, Eq. Heatdisc):  T' = Fo (T_{i+1} + T_{i-1}) + (1 - 2 Fo) T_i
 //   KS    (Appendix C, Eqs. KSDisc, RKm, RKf): 5-point central differences,
@@ -44,13 +44,13 @@ struct Heat {
     static constexpr int R = 1, S = 1, NV = 1;
     template <int P>
     SW_HD static void level(double (&dst)[NV][P], const double (&ext)[NV][P + 2 * R],
-                            bool /*predictor*/, const Consts &c, int klo, int khi)
+                            bool /*predictor*/, const Consts &c, const bool (&in)[P])
     {
 #pragma unroll
         for (int k = 0; k < P; ++k) {
             double s = ext[0][k + 2] + ext[0][k];
             double v = c.fo * s + c.c0 * ext[0][k + 1];
-            if (k >= klo && k < khi) dst[0][k] = v;
+            if (in[k]) dst[0][k] = v;
         }
     }
 };
@@ -69,13 +69,13 @@ struct KS {
     }
     template <int P>
     SW_HD static void level(double (&dst)[NV][P], const double (&ext)[NV][P + 2 * R],
-                            bool predictor, const Consts &c, int klo, int khi)
+                            bool predictor, const Consts &c, const bool (&in)[P])
     {
 #pragma unroll
         for (int k = 0; k < P; ++k) {
             double f = rhs(ext[0][k], ext[0][k + 1], ext[0][k + 2], ext[0][k + 3], ext[0][k + 4], c);
             double v = predictor ? ext[0][k + 2] + c.hdt * f : dst[0][k] + c.dt * f;
-            if (k >= klo && k < khi) dst[0][k] = v;
+            if (in[k]) dst[0][k] = v;
         }
     }
 };
@@ -133,7 +133,7 @@ struct Euler {
 
     template <int P>
     SW_HD static void level(double (&dst)[NV][P], const double (&ext)[NV][P + 2 * R],
-                            bool predictor, const Consts &c, int klo, int khi)
+                            bool predictor, const Consts &c, const bool (&in)[P])
     {
         double pres[P + 2 * R];
 #pragma unroll
@@ -156,12 +156,12 @@ struct Euler {
             double qc[3] = {ext[0][k + 3], ext[1][k + 3], ext[2][k + 3]};
             double qd[3] = {ext[0][k + 4], ext[1][k + 4], ext[2][k + 4]};
             flux(qa, qb, qc, qd, pres[k + 1], pres[k + 2], pres[k + 3], pres[k + 4], c, fnext);
-            const bool in = k >= klo && k < khi;
+            const bool ink = in[k];
 #pragma unroll
             for (int v = 0; v < 3; ++v) {
                 double base = predictor ? ext[v][k + 2] : dst[v][k];
                 double val = base + coef * (fprev[v] - fnext[v]);
-                if (in) dst[v][k] = val;
+                if (ink) dst[v][k] = val;
                 fprev[v] = fnext[v];
             }
         }

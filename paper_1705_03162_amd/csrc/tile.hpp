@@ -36,7 +36,7 @@ enum PhaseKind : int32_t { PH_UP = 0, PH_DIAMOND = 1, PH_DOWN = 2 };
 
 // Largest work-group for which a tile kernel is compiled: the two rows take
 // 2*nv*P doubles per lane, and the register file must hold them for every wave.
-constexpr int max_threads_for(int nv, int P) { return nv > 1 ? 256 : (P >= 16 ? 512 : 1024); }
+constexpr int max_threads_for(int nv, int P) { return nv > 1 ? (P >= 8 ? 256 : 512) : (P >= 16 ? 512 : 1024); }
 
 struct TileArgs {
     double *state;     // [nv][n]
@@ -199,6 +199,40 @@ SW_HD void lane_store(const TileArgs &a, int64_t j, int g, const double (&r0)[Sc
             }
         }
     }
+}
+
+// ---- per-element lane bounds with residues fixed by the level's position ----
+//
+// The computed set [lo, hi) moves by exactly r per level, so lo and hi modulo P
+// depend only on s modulo G = max(P/r, 2) and on whether the set is widening
+// (Down, lower half of a Diamond: lo = w/2 - r s) or narrowing (Up, upper half of
+// a Diamond: lo = w/2 - r (H - s) or w/2 - r (2H - s)).  With levels unrolled in
+// groups that start at s = 1 mod G, the residues are compile-time constants and
+// element k of lane l is computed iff la <= l < lb below.
+SW_HD constexpr int group_len(int P, int R) { return P / R < 2 ? 2 : P / R; }
+SW_HD constexpr int pos_mod(int x, int m) { return ((x % m) + m) % m; }
+SW_HD int floor_div_pow2(int x, int P) { return x >= 0 ? x / P : -((-x + P - 1) / P); }
+SW_HD bool level_widening(const TileArgs &a, int s)
+{
+    return a.kind == PH_DOWN || (a.kind == PH_DIAMOND && s <= a.H);
+}
+SW_HD void element_lane_bounds(int P, int R, bool widening, int s_mod, int lo, int hi, int base,
+                               int k, int &la, int &lb)
+{
+    const int ra = pos_mod(widening ? -R * s_mod : R * s_mod, P);  // lo mod P
+    const int rb = pos_mod(widening ? R * s_mod : -R * s_mod, P);  // hi mod P
+    const int qa = floor_div_pow2(lo, P) - base, qb = floor_div_pow2(hi, P) - base;
+    la = k >= ra ? qa : qa + 1;
+    lb = k < rb ? qb + 1 : qb;
+}
+
+// Lanes (numbered from `base`) that hold at least one computed point: [lmin, lmax).
+SW_HD void element_lane_span(int P, int R, bool widening, int s_mod, int lo, int hi, int base,
+                             int &lmin, int &lmax)
+{
+    const int rb = pos_mod(widening ? R * s_mod : -R * s_mod, P);
+    lmin = floor_div_pow2(lo, P) - base;                       // element P-1 is past lo's residue
+    lmax = floor_div_pow2(hi, P) - base + (rb > 0 ? 1 : 0);    // element 0 is below hi's residue
 }
 
 // Lane-local bounds [klo, khi) of the points computed at relative level s.

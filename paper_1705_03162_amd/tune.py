@@ -1,0 +1,125 @@
+"""Autotuner for the swept tile shape.
+
+For each (scheme, floor(log2 n)) it times swept solves over every legal
+(width, threads) pair that divides n and writes the fastest to
+tune_gfx950.txt next to libswept.so; swept_plan() reads that table whenever
+the caller does not fix a shape.  The choice never changes results: the
+decomposition is bitwise identical for every shape (the GPU tests check it).
+The paper likewise reports the best block size per grid size (Sec. 5).
+
+    python -m paper_1705_03162_amd.tune [--schemes heat,ks,euler] [--log2n 12-20]
+"""
+from __future__ import annotations
+
+import argparse
+import os
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+TABLE = os.path.join(HERE, "tune_gfx950.txt")
+
+POINTS_PER_LANE = (1, 2, 4, 8, 16)
+WAVES = (1, 2, 4, 8, 16)
+
+
+def legal(scheme: int, P: int, threads: int) -> bool:
+    r = 1 if scheme == 0 else 2
+    if P < r:
+        return False
+    if scheme == 2 and P > 8:
+        return False
+    max_t = (256 if P >= 8 else 512) if scheme == 2 else (512 if P >= 16 else 1024)
+    return threads <= max_t
+
+
+def candidate_shapes(scheme: int, n: int):
+    out = []
+    for P in POINTS_PER_LANE:
+        for nw in WAVES:
+            t = 64 * nw
+            w = P * t
+            if legal(scheme, P, t) and n % w == 0:
+                out.append((w, t))
+    return out
+
+
+def _problem(scheme: int, log2n: int, nsteps: int):
+    import workloads as W
+    n = 1 << log2n
+    if scheme == W.HEAT:
+        return W.heat_problem(n, nsteps), W.fourier_ic(n, seed=log2n)
+    if scheme == W.KS:
+        return W.ks_problem(n, nsteps), W.fourier_ic(n, seed=log2n)
+    return W.sod_problem(n, nsteps), W.sod_ic(n)
+
+
+def time_shape(sw, torch, prob, ic, width, threads, reps):
+    with sw.Plan(prob, width=width, threads=threads) as plan:
+        x0 = torch.tensor(ic, dtype=torch.float64, device="cuda")
+        x = x0.clone()
+        plan.swept(x)                # warm: graph capture
+        best = float("inf")
+        for _ in range(reps):
+            x.copy_(x0)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            plan.swept(x)
+            torch.cuda.synchronize()
+            best = min(best, time.perf_counter() - t0)
+    return best
+
+
+def tune(schemes=(0, 1, 2), log2ns=range(12, 21), target_s: float = 0.02, reps: int = 3,
+         table: str = TABLE, log=print):
+    import torch
+
+    import paper_1705_03162_amd as sw
+    rows = []
+    for scheme in schemes:
+        for lg in log2ns:
+            n = 1 << lg
+            shapes = candidate_shapes(scheme, n)
+            if not shapes:
+                continue
+            # choose a step count that takes ~target_s with the default shape
+            steps = 200
+            prob, ic = _problem(scheme, lg, steps)
+            t = time_shape(sw, torch, prob, ic, *shapes[len(shapes) // 2], reps=1)
+            steps = int(min(50_000, max(200, steps * target_s / max(t, 1e-6))))
+            prob, ic = _problem(scheme, lg, steps)
+            results = []
+            for w, th in shapes:
+                t = time_shape(sw, torch, prob, ic, w, th, reps)
+                results.append((t, w, th))
+            results.sort()
+            t, w, th = results[0]
+            rate = n * steps / t
+            log(f"scheme={scheme} log2n={lg} steps={steps} best w={w} T={th} "
+                f"{rate:.3e} pt-upd/s; worst {n * steps / results[-1][0]:.3e}")
+            rows.append((scheme, lg, w, th, rate, steps))
+    with open(table + ".tmp", "w") as f:
+        f.write("# scheme log2n width threads  (point-updates/s, steps timed)\n")
+        for scheme, lg, w, th, rate, steps in rows:
+            f.write(f"{scheme} {lg} {w} {th}  # {rate:.4e} {steps}\n")
+    os.replace(table + ".tmp", table)
+    return rows
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--schemes", default="heat,ks,euler")
+    ap.add_argument("--log2n", default="12-20")
+    ap.add_argument("--table", default=TABLE)
+    ap.add_argument("--target-ms", type=float, default=20.0)
+    args = ap.parse_args()
+    names = {"heat": 0, "ks": 1, "euler": 2}
+    schemes = [names[s] for s in args.schemes.split(",")]
+    a, b = (int(x) for x in args.log2n.split("-"))
+    sys.path.insert(0, os.path.dirname(HERE))
+    tune(schemes, range(a, b + 1), target_s=args.target_ms / 1000.0, table=args.table,
+         log=lambda m: print(m, flush=True))
+
+
+if __name__ == "__main__":
+    main()

@@ -10,6 +10,7 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <stdexcept>
 #include <string>
 #include <vector>
 
@@ -33,6 +34,9 @@ void run_phase(const Geom &g, const TileArgs &a)
         const int gw = a.w / (2 * P) - 1;
         for (int s = 1; s <= nlev; ++s) {
             const bool odd = (s & 1) != 0;
+            // like the kernel: the points just outside the tile are supplied only at the
+            // widest level of a Diamond/Down (the only level whose stencil reaches them)
+            const bool outer = s == a.H && a.kind != PH_UP;
             for (int l = 0; l < lanes; ++l) {
                 double (&src)[NV][P] = odd ? L[l].r0 : L[l].r1;
                 double (&dst)[NV][P] = odd ? L[l].r1 : L[l].r0;
@@ -40,18 +44,36 @@ void run_phase(const Geom &g, const TileArgs &a)
                 for (int v = 0; v < NV; ++v) {
                     for (int k = 0; k < P; ++k) ext[v][R + k] = src[v][k];
                     for (int i = 0; i < R; ++i) {
-                        ext[v][i] = l > 0 ? (odd ? L[l - 1].r0 : L[l - 1].r1)[v][P - R + i] : L[0].hl[v][i];
+                        ext[v][i] = l > 0 ? (odd ? L[l - 1].r0 : L[l - 1].r1)[v][P - R + i]
+                                          : (outer ? L[0].hl[v][i] : 0.0);
                         ext[v][R + P + i] = l < lanes - 1 ? (odd ? L[l + 1].r0 : L[l + 1].r1)[v][i]
-                                                          : L[lanes - 1].hr[v][i];
+                                                          : (outer ? L[lanes - 1].hr[v][i] : 0.0);
                     }
                     if (wall && l == gw)
                         for (int i = 0; i < R; ++i) ext[v][R + P + i] = a.c.ghost_r[v];
                     if (wall && l == gw + 1)
                         for (int i = 0; i < R; ++i) ext[v][i] = a.c.ghost_l[v];
                 }
-                int klo, khi;
+                // element masks exactly as the kernel derives them (residues from s mod G)
+                const int m = half_width(a, s);
+                const int lo = a.w / 2 - R * m, hi = a.w / 2 + R * m;
+                const int smod = s % group_len(P, R);
+                bool in[P];
+                for (int k = 0; k < P; ++k) {
+                    int la, lb;
+                    element_lane_bounds(P, R, level_widening(a, s), smod, lo, hi, 0, k, la, lb);
+                    in[k] = l >= la && l < lb;
+                }
+                int klo, khi;  // cross-check against the direct bounds
                 lane_bounds(a, s, l, P, R, klo, khi);
-                Sch::template level<P>(dst, ext, odd, a.c, klo, khi);
+                for (int k = 0; k < P; ++k)
+                    if (in[k] != (k >= klo && k < khi)) throw std::logic_error("element mask mismatch");
+                int lmin, lmax;  // lanes the kernel does not skip
+                element_lane_span(P, R, level_widening(a, s), smod, lo, hi, 0, lmin, lmax);
+                if (klo < khi && !(l >= lmin && l < lmax)) throw std::logic_error("skipped an active lane");
+                if (klo >= khi && l >= lmin && l < lmax && (l == lmin || l == lmax - 1) && lmax - lmin > 2)
+                    throw std::logic_error("lane span not tight");
+                Sch::template level<P>(dst, ext, odd, a.c, in);
             }
         }
         for (int l = 0; l < lanes; ++l) lane_store<Sch, P>(a, j, l, L[l].r0, L[l].r1);
@@ -87,9 +109,13 @@ extern "C" int hostsim_swept(const sw_problem *p, int width, int threads, double
     if ((rc = make_geom(*p, width, threads, &g, &err))) return rc;
     if (!g.swept_ok) return SW_EUNSUPPORTED;
     Consts c = make_consts(*p);
-    if (p->scheme == SW_HEAT) return run_all<Heat>(g, c, state);
-    if (p->scheme == SW_KS) return run_all<KS>(g, c, state);
-    return run_all<Euler>(g, c, state);
+    try {
+        if (p->scheme == SW_HEAT) return run_all<Heat>(g, c, state);
+        if (p->scheme == SW_KS) return run_all<KS>(g, c, state);
+        return run_all<Euler>(g, c, state);
+    } catch (const std::exception &) {
+        return -100;  // internal consistency check failed
+    }
 }
 
 // Launch sequence of a plan: out[3*i .. 3*i+2] = (kind, levels, offset).
