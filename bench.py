@@ -91,6 +91,107 @@ def rate_of(sw, torch, prob, ic, kind, flags=0, reps=2):
     return prob.n * prob.nsteps / best, best, info, x
 
 
+def pct(xs, q):
+    return float(np.percentile(np.asarray(xs), q)) if len(xs) else None
+
+
+def ensemble_run(count=4096, nsteps=10_000, one_at_a_time_sample=512):
+    """4096 independent heat/KS solves of uneven N: one batched graph launch vs
+    the same solves one after another (each its own tuned plan), on the same GPU."""
+    import torch
+    import paper_1705_03162_amd as sw
+    members = W.ensemble(count=count, nsteps=nsteps)
+    ics = [W.ensemble_ic(m) for m in members]
+    upd = sum(m.problem.point_updates for m in members)
+    states = [torch.tensor(ic, dtype=torch.float64, device="cuda") for ic in ics]
+    torch.cuda.synchronize()
+    with sw.Batch(budget_bytes=200 << 30) as b:
+        tickets = [b.submit(m.problem, x) for m, x in zip(members, states)]
+        t0 = time.perf_counter()
+        b.run()
+        torch.cuda.synchronize()
+        makespan = time.perf_counter() - t0
+        infos = [b.info(t) for t in tickets]
+    start = min(i["start_s"] for i in infos)
+    lat = [i["end_s"] - start for i in infos]
+    batched = {"solves": count, "point_updates": upd, "seconds": makespan, "rate": upd / makespan,
+               "p50_s": pct(lat, 50), "p99_s": pct(lat, 99)}
+    # one solve at a time: a seeded sample, extrapolated by point-updates
+    rng = np.random.default_rng(7)
+    idx = rng.choice(count, size=min(one_at_a_time_sample, count), replace=False)
+    t_alone, upd_alone, lat_alone = 0.0, 0, []
+    for j in idx:
+        m = members[j]
+        with sw.Plan(m.problem) as plan:
+            x = torch.tensor(ics[j], dtype=torch.float64, device="cuda")
+            plan.swept(x)                 # capture the graph outside the timing
+            x.copy_(torch.tensor(ics[j], dtype=torch.float64, device="cuda"))
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            plan.swept(x)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+        t_alone += dt
+        upd_alone += m.problem.point_updates
+        lat_alone.append(dt)
+    alone_rate = upd_alone / t_alone
+    # FIFO completion times if every solve ran alone, back to back from t = 0
+    est = upd / alone_rate
+    return {"batched": batched,
+            "one_at_a_time": {"sampled_solves": len(idx), "rate": alone_rate,
+                              "estimated_seconds": est, "solve_p50_s": pct(lat_alone, 50),
+                              "solve_p99_s": pct(lat_alone, 99)},
+            "speedup": batched["rate"] / alone_rate}
+
+
+def serve_run(rate=2000.0, duration_s=0.25, seed=5, max_slots=0, fifo=True):
+    """Poisson arrivals of mixed heat/KS/Sod solves into a served batch (continuous
+    batching, 200 GB budget); latency = completion - arrival."""
+    import torch
+    import paper_1705_03162_amd as sw
+    trace = W.poisson_trace(rate=rate, duration_s=duration_s, seed=seed)
+    ics = [W.request_ic(r) for r in trace]
+    states = [torch.tensor(ic, dtype=torch.float64, device="cuda") for ic in ics]
+    torch.cuda.synchronize()
+    upd = sum(r.problem.point_updates for r in trace)
+    with sw.Batch(budget_bytes=200 << 30, max_slots=max_slots, serve=True) as b:
+        t0 = time.perf_counter()
+        tickets = []
+        for r, x in zip(trace, states):
+            delay = r.arrival_s - (time.perf_counter() - t0)
+            if delay > 0:
+                time.sleep(delay)
+            tickets.append(b.submit(r.problem, x))
+        for t in tickets:
+            b.wait(t)
+        wall = time.perf_counter() - t0
+        infos = [b.info(t) for t in tickets]
+    lat = [i["end_s"] - i["submit_s"] for i in infos]
+    out = {"requests": len(trace), "offered_rate_per_s": rate, "arrival_window_s": duration_s,
+           "point_updates": upd, "wall_s": wall, "throughput_point_updates_s": upd / wall,
+           "p50_latency_s": pct(lat, 50), "p99_latency_s": pct(lat, 99)}
+    if fifo:
+        # one solve at a time, first come first served, on the same trace
+        lat_f = []
+        t0 = time.perf_counter()
+        for r, ic in zip(trace, ics):
+            now = time.perf_counter() - t0
+            if now < r.arrival_s:
+                time.sleep(r.arrival_s - now)
+            with sw.Plan(r.problem, flags=sw.SW_TUNE_NO_GRAPH) as plan:
+                x = torch.tensor(ic, dtype=torch.float64, device="cuda")
+                if plan.info()["swept_ok"]:
+                    plan.swept(x)
+                else:
+                    plan.classic(x)
+                torch.cuda.synchronize()
+            lat_f.append(time.perf_counter() - t0 - r.arrival_s)
+        wall_f = time.perf_counter() - t0
+        out["one_at_a_time"] = {"wall_s": wall_f, "throughput_point_updates_s": upd / wall_f,
+                                "p50_latency_s": pct(lat_f, 50), "p99_latency_s": pct(lat_f, 99)}
+    return out
+
+
 def suite_sweep(schemes, log2ns, max_steps):
     """One JSON line per (scheme, N): swept vs classic (graph and stream launches)."""
     import torch
@@ -121,8 +222,9 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-batch", action="store_true", help="skip the ensemble and serving runs")
     ap.add_argument("--profile-reps", type=int, default=30)
-    ap.add_argument("--suite", default="main", choices=["main", "sweep", "euler"],
+    ap.add_argument("--suite", default="main", choices=["main", "sweep", "euler", "ensemble", "serve", "kernel"],
                     help="main: the one-line benchmark; sweep/euler: per-N swept vs classic lines")
     ap.add_argument("--max-steps", type=int, default=20_000)
     args = ap.parse_args()
@@ -130,6 +232,31 @@ def main():
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); every box here has one "
               "GPU and nothing in this build uses a second.", file=sys.stderr)
         sys.exit(2)
+    if args.suite == "kernel":
+        # for hardware-counter runs: a known-size device copy (calibrates FETCH/WRITE)
+        # and a few launches of the dominant kernel (KS Diamond at N = 2^20)
+        import torch
+        import paper_1705_03162_amd as sw
+        src = torch.ones(1 << 25, dtype=torch.float64, device="cuda")   # 256 MiB
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        prob, ic = W.cfg_sweep(W.KS, LOG2N)
+        with sw.Plan(prob) as plan:
+            x = torch.tensor(ic, dtype=torch.float64, device="cuda")
+            us = plan.profile_phase(x, kind=1, reps=args.profile_reps)
+            info = plan.info()
+        print(json.dumps({"copy_bytes": 2 * src.numel() * 8, "diamond_avg_us": us,
+                          "width": info["width"], "threads": info["threads"],
+                          "levels_per_phase": info["levels_per_phase"], "n": prob.n}), flush=True)
+        return
+    if args.suite == "ensemble":
+        print(json.dumps(ensemble_run()), flush=True)
+        return
+    if args.suite == "serve":
+        for rate, dur in ((2000.0, 1.0), (200.0, 5.0)):
+            print(json.dumps(serve_run(rate=rate, duration_s=dur)), flush=True)
+        return
     if args.suite != "main":
         schemes = [W.EULER] if args.suite == "euler" else [W.HEAT, W.KS]
         suite_sweep(schemes, range(12, 21), args.max_steps)
@@ -238,6 +365,15 @@ def main():
     }
     for pl in plans:
         pl.close()
+    if not args.no_batch:
+        log("ensemble (4096 solves) ...")
+        result["batch"] = {"ensemble": ensemble_run()}
+        log("served Poisson trace ...")
+        result["batch"]["serve"] = serve_run(rate=2000.0, duration_s=0.25)
+        e = result["batch"]["ensemble"]
+        log(f"ensemble: batched {e['batched']['rate']:.3e} pt-upd/s in {e['batched']['seconds']:.2f} s, "
+            f"one-at-a-time {e['one_at_a_time']['rate']:.3e}; serve p50 "
+            f"{result['batch']['serve']['p50_latency_s']:.3f} s p99 {result['batch']['serve']['p99_latency_s']:.3f} s")
     if not args.no_cpu:
         log("cpu baseline (oracle) ...")
         result["cpu_baseline"] = cpu_baseline()

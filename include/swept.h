@@ -144,11 +144,25 @@ int swept_profile_phase(sw_plan *plan, double *d_state, int32_t kind, int32_t re
                         void *hip_stream, double *avg_us);
 
 /* ---- batched / served solves ------------------------------------------- */
+/* Many independent solves share launches.  The paper runs one solve at a time;
+ * batching many solves of uneven n into shared phase launches, and serving
+ * them continuously, are this library's additions around its swept phases.
+ * Each solve keeps the exact results of swept_solve on the same problem. */
+#define SW_BATCH_SERVE 1          /* a worker thread admits and advances solves continuously */
 typedef struct {
-    int64_t budget_bytes;     /* device bytes the batch may hold for resident state + edges */
+    int64_t budget_bytes;     /* device bytes the batch may hold for resident solves (state + edges,
+                                 counted as 3 * n * nvars * 8 per solve) */
     int32_t max_slots;        /* maximum resident solves (0 = unlimited) */
-    int32_t flags;            /* reserved, 0 */
+    int32_t flags;            /* 0 (ensemble: batch_run) or SW_BATCH_SERVE */
 } sw_batch_config;
+
+typedef struct {
+    int32_t status;           /* SW_TICKET_* */
+    int32_t swept;            /* 1: swept phases in shared launches; 0: classic fallback */
+    int32_t width;            /* tile width used (swept) */
+    int32_t phases;           /* swept phases of the solve */
+    double  submit_s, start_s, end_s;  /* host steady-clock seconds: submitted, admitted, finished */
+} sw_ticket_info;
 
 typedef struct sw_batch sw_batch;
 
@@ -159,16 +173,28 @@ typedef struct sw_batch sw_batch;
 #define SW_TICKET_FAILED   3
 #define SW_TICKET_CANCELLED 4
 
+/* Create a batch on the current device.  With SW_BATCH_SERVE a worker thread
+ * starts at once. */
 int  batch_create(const sw_batch_config *config, sw_batch **out);
-/* Queue one solve on caller-owned device state (layout as above).  The ticket
- * identifies it in later calls. */
+/* Queue one solve on caller-owned device state (layout as above; the caller keeps
+ * it alive and untouched until the ticket is done).  SW_EBUSY if the solve alone
+ * exceeds the budget.  Thread-safe. */
 int  batch_submit(sw_batch *batch, const sw_problem *problem, double *d_state, uint64_t *ticket);
-/* Ensemble mode: run every queued solve to completion with persistent launches
- * on `hip_stream`, then return (synchronous). */
+/* Ensemble mode: run every queued solve to completion, then return
+ * (synchronous).  Solves are admitted in submission order in waves that fit the
+ * budget and slot limit; each wave runs as one HIP graph launch holding one
+ * batched launch per phase index and tile-width group. */
 int  batch_run(sw_batch *batch, void *hip_stream);
 int  batch_poll(sw_batch *batch, uint64_t ticket, int32_t *status_out);
+/* Block until the ticket is done, cancelled or failed, or timeout_us passes
+ * (negative: no limit).  SW_ENOTREADY on timeout. */
 int  batch_wait(sw_batch *batch, uint64_t ticket, int64_t timeout_us);
+/* Cancel a ticket that has not started (SW_EBUSY once it runs). */
 int  batch_cancel(sw_batch *batch, uint64_t ticket);
+/* Status and timing of one ticket. */
+int  batch_ticket_info(sw_batch *batch, uint64_t ticket, sw_ticket_info *out);
+/* Stop the worker (served mode; queued tickets are cancelled, running ones
+ * finish), free the batch's device memory. */
 void batch_destroy(sw_batch *batch);
 
 /* ---- diagnostics ------------------------------------------------------- */

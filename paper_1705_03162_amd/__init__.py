@@ -112,10 +112,15 @@ def classic_solve(plan: Plan, state, stream=None):
 
 
 class Batch:
-    """Independent solves admitted under a device-memory budget (batch_* API)."""
+    """Independent solves admitted under a device-memory budget (batch_* API).
 
-    def __init__(self, budget_bytes: int, max_slots: int = 0):
-        cfg = N.SwBatchConfig(int(budget_bytes), int(max_slots), 0)
+    serve=False: queue solves with submit(), then run() executes them all (ensemble).
+    serve=True: a worker thread admits and advances solves as they are submitted
+    (continuous batching); use poll()/wait()/info().
+    """
+
+    def __init__(self, budget_bytes: int, max_slots: int = 0, serve: bool = False):
+        cfg = N.SwBatchConfig(int(budget_bytes), int(max_slots), N.SW_BATCH_SERVE if serve else 0)
         h = ctypes.c_void_p()
         N.check(N.lib().batch_create(ctypes.byref(cfg), ctypes.byref(h)), "batch_create")
         self._h = h
@@ -142,6 +147,12 @@ class Batch:
 
     def cancel(self, ticket: int):
         N.check(N.lib().batch_cancel(self._h, ctypes.c_uint64(ticket)), "batch_cancel")
+
+    def info(self, ticket: int) -> dict:
+        i = N.SwTicketInfo()
+        N.check(N.lib().batch_ticket_info(self._h, ctypes.c_uint64(ticket), ctypes.byref(i)),
+                "batch_ticket_info")
+        return {k: getattr(i, k) for k, _ in N.SwTicketInfo._fields_}
 
     def close(self):
         if getattr(self, "_h", None):

@@ -55,6 +55,15 @@ class SwBatchConfig(ctypes.Structure):
                 ("flags", ctypes.c_int32)]
 
 
+SW_BATCH_SERVE = 1
+
+
+class SwTicketInfo(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("swept", ctypes.c_int32), ("width", ctypes.c_int32),
+                ("phases", ctypes.c_int32), ("submit_s", ctypes.c_double),
+                ("start_s", ctypes.c_double), ("end_s", ctypes.c_double)]
+
+
 def problem_struct(problem, limiter: int = 0) -> SwProblem:
     """Fill an sw_problem from any object with the workloads.Problem fields."""
     s = SwProblem()
@@ -94,6 +103,7 @@ SIGNATURES = {
     "batch_poll": (ctypes.c_int, [_VP, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int32)]),
     "batch_wait": (ctypes.c_int, [_VP, ctypes.c_uint64, ctypes.c_int64]),
     "batch_cancel": (ctypes.c_int, [_VP, ctypes.c_uint64]),
+    "batch_ticket_info": (ctypes.c_int, [_VP, ctypes.c_uint64, ctypes.POINTER(SwTicketInfo)]),
     "batch_destroy": (None, [_VP]),
     "sw_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "sw_last_error": (ctypes.c_char_p, []),
@@ -110,7 +120,9 @@ def lib():
                 "(python -c 'import __graft_entry__ as g; g.build()')")
         L = ctypes.CDLL(LIB_PATH)
         for name, (res, args) in SIGNATURES.items():
-            fn = getattr(L, name)
+            fn = getattr(L, name, None)
+            if fn is None:   # older build: the entry point fails when called, not at load
+                continue
             fn.restype = res
             fn.argtypes = args
         _lib = L

@@ -1,24 +1,56 @@
 // Batched solves (batch_* entry points of include/swept.h).
 //
-// A batch holds tickets for independent solves on caller-owned device states.
+// Ensemble mode (batch_run): queued solves are grouped by (scheme, points per
+// lane); each group advances all its solves together, one launch per phase
+// index covering every tile of every solve still running.  Solves are sorted
+// by phase count, so the solves still running at phase p are always a prefix of
+// the group's (solve, tile) table and one table serves every launch.  The
+// launches of all groups (and timing events) are captured into one HIP graph
+// and replayed with a single launch.  Kernel boundaries order the phases, which
+// keeps edge data coherent across the MI355X's eight XCD-private L2 caches
+// without device-side flags.
+//
+// Served mode (flags SW_BATCH_SERVE): a worker thread admits queued solves as
+// memory and slots free up and runs ticks; each tick advances every resident
+// solve by one phase with one launch per group (continuous batching).
+//
 // Admission is by a device-memory budget: a resident solve holds its state plus
-// its edge slots and scratch (about 3 n nvars doubles).
+// its edge slots (about 3 n nvars doubles).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <atomic>
 #include <chrono>
+#include <condition_variable>
 #include <cstring>
+#include <deque>
+#include <map>
 #include <mutex>
 #include <new>
 #include <thread>
 #include <vector>
 
 #include "api_internal.hpp"
+#include "kernels.hpp"
 #include "plan_core.hpp"
 #include "swept.h"
 
 using namespace sw;
 
+#define BHIP(expr)                                            \
+    do {                                                      \
+        hipError_t _e = (expr);                               \
+        if (_e != hipSuccess) return sw::hip_fail(_e, #expr); \
+    } while (0)
+
 namespace {
+
+using Clock = std::chrono::steady_clock;
+
+double now_s()
+{
+    return std::chrono::duration<double>(Clock::now().time_since_epoch()).count();
+}
 
 struct Ticket {
     uint64_t id = 0;
@@ -26,7 +58,13 @@ struct Ticket {
     double *state = nullptr;
     int32_t status = SW_TICKET_QUEUED;
     int64_t bytes = 0;
-    sw_plan *plan = nullptr;
+    double t_submit = 0, t_start = 0, t_end = 0;
+    // swept geometry when batched
+    bool swept = false;
+    int P = 0;
+    Geom geom;
+    double *edges = nullptr;
+    int32_t phase = 0;
 };
 
 int64_t resident_bytes(const sw_problem &p)
@@ -34,25 +72,450 @@ int64_t resident_bytes(const sw_problem &p)
     return 3 * p.n * (int64_t)scheme_nvars(p.scheme) * (int64_t)sizeof(double);
 }
 
+// Tile shape for a batched solve: one-wave tiles (no barriers), the most points
+// per lane (up to 8) that still divide n.
+bool batch_shape(const sw_problem &p, int *P, Geom *g)
+{
+    for (int pp = 8; pp >= 1; pp /= 2) {
+        if (!legal_points_per_lane(p.scheme, pp)) continue;
+        const int w = 64 * pp;
+        if (p.n % w != 0) continue;
+        std::string err;
+        if (make_geom(p, w, 64, g, &err) != SW_OK) continue;
+        *P = pp;
+        return true;
+    }
+    return false;
+}
+
+// Device arena: large chunks, first-fit sub-allocation, freed only on destroy.
+struct Arena {
+    struct Chunk { char *base; size_t size; std::map<size_t, size_t> free; };  // offset -> size
+    std::vector<Chunk> chunks;
+    static constexpr size_t kChunk = (size_t)256 << 20;
+    static constexpr size_t kAlign = 256;
+
+    void *alloc(size_t bytes)
+    {
+        bytes = (bytes + kAlign - 1) / kAlign * kAlign;
+        for (Chunk &c : chunks) {
+            for (auto it = c.free.begin(); it != c.free.end(); ++it) {
+                if (it->second >= bytes) {
+                    size_t off = it->first, sz = it->second;
+                    c.free.erase(it);
+                    if (sz > bytes) c.free[off + bytes] = sz - bytes;
+                    return c.base + off;
+                }
+            }
+        }
+        size_t sz = std::max(kChunk, bytes);
+        void *p = nullptr;
+        if (hipMalloc(&p, sz) != hipSuccess) { (void)hipGetLastError(); return nullptr; }
+        Chunk c{(char *)p, sz, {}};
+        if (sz > bytes) c.free[bytes] = sz - bytes;
+        chunks.push_back(std::move(c));
+        return p;
+    }
+    void release(void *p, size_t bytes)
+    {
+        if (!p) return;
+        bytes = (bytes + kAlign - 1) / kAlign * kAlign;
+        for (Chunk &c : chunks) {
+            char *cp = (char *)p;
+            if (cp < c.base || cp >= c.base + c.size) continue;
+            size_t off = (size_t)(cp - c.base);
+            auto nx = c.free.lower_bound(off);
+            // merge with the following block
+            if (nx != c.free.end() && nx->first == off + bytes) { bytes += nx->second; nx = c.free.erase(nx); }
+            // merge with the preceding block
+            if (nx != c.free.begin()) {
+                auto pv = std::prev(nx);
+                if (pv->first + pv->second == off) { pv->second += bytes; return; }
+            }
+            c.free[off] = bytes;
+            return;
+        }
+    }
+    void destroy()
+    {
+        for (Chunk &c : chunks) (void)hipFree(c.base);
+        chunks.clear();
+    }
+};
+
+// Device copy of one group's descriptors and (solve, tile) items.
+struct GroupBuf {
+    int scheme = 0, P = 1;
+    std::vector<SolveDesc> desc;
+    std::vector<int2> items;
+    std::vector<int64_t> prefix;   // items of the first k solves
+    SolveDesc *d_desc = nullptr;
+    int2 *d_items = nullptr;
+    int grid_cap = 1;
+};
+
+SolveDesc make_desc(const Ticket &t)
+{
+    SolveDesc d{};
+    d.state = t.state;
+    d.edges = t.edges;
+    d.n = t.geom.n;
+    d.K = t.geom.K;
+    d.Q = t.geom.Q;
+    d.rem = t.geom.rem;
+    d.w = t.geom.w;
+    d.H = t.geom.H;
+    d.E = t.geom.E;
+    d.dirichlet = t.geom.bc == SW_DIRICHLET ? 1 : 0;
+    d.nphases = phase_count(t.geom.Q, t.geom.rem);
+    d.phase = t.phase;
+    d.c = make_consts(t.prob);
+    return d;
+}
+
+int num_cus()
+{
+    static int cached = 0;
+    if (!cached) {
+        int dev = 0, n = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && n > 0)
+            cached = n;
+        else
+            cached = 256;
+    }
+    return cached;
+}
+
 }  // namespace
 
 struct sw_batch {
     sw_batch_config cfg{};
-    std::vector<Ticket> tickets;
+    std::deque<Ticket> tickets;    // indexable by id - 1; push_back keeps references valid,
+                                   // so the served worker may hold Ticket pointers
     uint64_t next_id = 1;
     std::mutex mu;
+    std::condition_variable cv;
+    Arena arena;
+    // served mode
+    bool serve = false;
+    bool stop = false;
+    std::thread worker;
+    hipStream_t stream = nullptr;
+    int device = -1;
+    std::deque<uint64_t> queue;    // waiting tickets (served mode)
+    int64_t resident = 0;
+    int nresident = 0;
+    int64_t ticks = 0;
+    std::string worker_error;
 };
+
+namespace {
+
+Ticket *find_ticket(sw_batch *b, uint64_t id)
+{
+    if (id == 0 || id > b->tickets.size()) return nullptr;
+    return &b->tickets[id - 1];
+}
+
+// Run a set of admitted swept tickets to completion as one graph (ensemble mode).
+int run_ensemble(sw_batch *b, std::vector<Ticket *> &ts, hipStream_t st)
+{
+    // allocate edges
+    for (Ticket *t : ts) {
+        t->edges = (double *)b->arena.alloc((size_t)t->geom.edge_doubles * sizeof(double));
+        if (!t->edges) return fail(SW_ENOMEM, "edge arena allocation failed");
+        t->phase = 0;
+    }
+    // group by (scheme, P), sort by phase count (descending)
+    std::map<std::pair<int, int>, std::vector<Ticket *>> groups;
+    for (Ticket *t : ts) groups[{t->prob.scheme, t->P}].push_back(t);
+    std::vector<GroupBuf> gb;
+    int max_phases = 0;
+    for (auto &kv : groups) {
+        auto &v = kv.second;
+        std::stable_sort(v.begin(), v.end(), [](const Ticket *x, const Ticket *y) {
+            return phase_count(x->geom.Q, x->geom.rem) > phase_count(y->geom.Q, y->geom.rem);
+        });
+        GroupBuf g;
+        g.scheme = kv.first.first;
+        g.P = kv.first.second;
+        g.prefix.push_back(0);
+        for (size_t s = 0; s < v.size(); ++s) {
+            g.desc.push_back(make_desc(*v[s]));
+            for (int64_t j = 0; j < v[s]->geom.K; ++j) g.items.push_back(make_int2((int)s, (int)j));
+            g.prefix.push_back((int64_t)g.items.size());
+            max_phases = std::max(max_phases, g.desc.back().nphases);
+        }
+        g.grid_cap = batch_blocks_per_cu(g.scheme, g.P) * num_cus();
+        gb.push_back(std::move(g));
+    }
+    int rc = SW_OK;
+    // device wall-clock stamps: stamps[0] before the first phase, stamps[p+1] after phase p
+    uint64_t *d_stamps = nullptr;
+    std::vector<uint64_t> stamps((size_t)max_phases + 1, 0);
+    BHIP(hipMalloc(&d_stamps, stamps.size() * sizeof(uint64_t)));
+    int clock_khz = 0;
+    {
+        int dev = 0;
+        BHIP(hipGetDevice(&dev));
+        BHIP(hipDeviceGetAttribute(&clock_khz, hipDeviceAttributeWallClockRate, dev));
+    }
+    for (GroupBuf &g : gb) {
+        BHIP(hipMalloc(&g.d_desc, g.desc.size() * sizeof(SolveDesc)));
+        BHIP(hipMalloc(&g.d_items, g.items.size() * sizeof(int2)));
+        BHIP(hipMemcpyAsync(g.d_desc, g.desc.data(), g.desc.size() * sizeof(SolveDesc), hipMemcpyHostToDevice, st));
+        BHIP(hipMemcpyAsync(g.d_items, g.items.data(), g.items.size() * sizeof(int2), hipMemcpyHostToDevice, st));
+    }
+    BHIP(hipStreamSynchronize(st));
+
+    // capture every phase launch of every group into one graph
+    hipStream_t cap = nullptr;
+    BHIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    BHIP(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+    hipError_t le = launch_stamp(d_stamps, 0, cap);
+    for (int p = 0; p < max_phases && le == hipSuccess; ++p) {
+        for (GroupBuf &g : gb) {
+            // solves still running at phase p: a prefix of the sorted group
+            size_t a = 0;
+            while (a < g.desc.size() && g.desc[a].nphases > p) ++a;
+            const int64_t nitems = g.prefix[a];
+            if (nitems == 0) continue;
+            const int grid = (int)std::min<int64_t>(nitems, g.grid_cap);
+            le = launch_batch_phase(g.scheme, g.P, g.d_desc, g.d_items, nitems, p, grid, cap);
+            if (le != hipSuccess) break;
+        }
+        if (le == hipSuccess) le = launch_stamp(d_stamps, p + 1, cap);
+    }
+    hipError_t ce = hipStreamEndCapture(cap, &graph);
+    if (le != hipSuccess) rc = hip_fail(le, "batched phase launch");
+    else if (ce != hipSuccess) rc = hip_fail(ce, "hipStreamEndCapture");
+    if (rc == SW_OK) {
+        hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) rc = hip_fail(e, "hipGraphInstantiate");
+    }
+    if (graph) (void)hipGraphDestroy(graph);
+    const double t0 = now_s();
+    if (rc == SW_OK) {
+        for (Ticket *t : ts) { t->status = SW_TICKET_RUNNING; t->t_start = t0; }
+        hipError_t e = hipGraphLaunch(exec, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) rc = hip_fail(e, "batched graph");
+    }
+    // completion time of a solve = the stamp after its last phase
+    if (rc == SW_OK &&
+        hipMemcpy(stamps.data(), d_stamps, stamps.size() * sizeof(uint64_t), hipMemcpyDeviceToHost) != hipSuccess)
+        rc = fail(SW_EDEVICE, "reading phase timestamps");
+    if (rc == SW_OK) {
+        const double tick_s = clock_khz > 0 ? 1.0 / (1000.0 * clock_khz) : 0.0;
+        for (Ticket *t : ts) {
+            const int np = phase_count(t->geom.Q, t->geom.rem);
+            t->t_end = t0 + (double)(stamps[(size_t)np] - stamps[0]) * tick_s;
+            t->status = SW_TICKET_DONE;
+        }
+    } else {
+        for (Ticket *t : ts) t->status = SW_TICKET_FAILED;
+    }
+    if (exec) (void)hipGraphExecDestroy(exec);
+    (void)hipStreamDestroy(cap);
+    (void)hipFree(d_stamps);
+    for (GroupBuf &g : gb) { (void)hipFree(g.d_desc); (void)hipFree(g.d_items); }
+    for (Ticket *t : ts) { b->arena.release(t->edges, (size_t)t->geom.edge_doubles * sizeof(double)); t->edges = nullptr; }
+    return rc;
+}
+
+// Solves no swept tile width divides: classic time-stepping through a plan.
+int run_classic_ticket(Ticket &t, hipStream_t st)
+{
+    sw_plan *plan = nullptr;
+    int rc = swept_plan(&t.prob, nullptr, &plan);
+    if (rc) { t.status = SW_TICKET_FAILED; return rc; }
+    t.status = SW_TICKET_RUNNING;
+    t.t_start = now_s();
+    rc = classic_solve(plan, t.state, st);
+    if (rc == SW_OK && hipStreamSynchronize(st) != hipSuccess) rc = fail(SW_EDEVICE, "classic batch solve");
+    swept_plan_destroy(plan);
+    t.t_end = now_s();
+    t.status = rc == SW_OK ? SW_TICKET_DONE : SW_TICKET_FAILED;
+    return rc;
+}
+
+// ---------------------------------------------------------------- served mode
+
+// Device tables of one group for one tick (grown on demand).
+struct TickTables {
+    int scheme = 0, P = 1;
+    SolveDesc *h_desc = nullptr, *d_desc = nullptr;
+    int2 *h_items = nullptr, *d_items = nullptr;
+    size_t cap_desc = 0, cap_items = 0;
+    int grid_cap = 1;
+    void ensure(size_t nd, size_t ni)
+    {
+        if (nd > cap_desc) {
+            size_t c = std::max(nd, 2 * cap_desc);
+            if (h_desc) (void)hipHostFree(h_desc);
+            if (d_desc) (void)hipFree(d_desc);
+            (void)hipHostMalloc((void **)&h_desc, c * sizeof(SolveDesc), 0);
+            (void)hipMalloc(&d_desc, c * sizeof(SolveDesc));
+            cap_desc = c;
+        }
+        if (ni > cap_items) {
+            size_t c = std::max(ni, 2 * cap_items);
+            if (h_items) (void)hipHostFree(h_items);
+            if (d_items) (void)hipFree(d_items);
+            (void)hipHostMalloc((void **)&h_items, c * sizeof(int2), 0);
+            (void)hipMalloc(&d_items, c * sizeof(int2));
+            cap_items = c;
+        }
+    }
+    void release()
+    {
+        if (h_desc) (void)hipHostFree(h_desc);
+        if (d_desc) (void)hipFree(d_desc);
+        if (h_items) (void)hipHostFree(h_items);
+        if (d_items) (void)hipFree(d_items);
+        h_desc = d_desc = nullptr;
+        h_items = d_items = nullptr;
+    }
+};
+
+void serve_loop(sw_batch *b)
+{
+    (void)hipSetDevice(b->device);
+    std::vector<Ticket *> resident;
+    std::map<std::pair<int, int>, TickTables> tables;
+    for (;;) {
+        std::vector<Ticket *> classic_now;
+        {
+            std::unique_lock<std::mutex> lk(b->mu);
+            for (;;) {
+                // admit in arrival order while memory and slots allow (head-of-line blocking keeps FIFO)
+                while (!b->queue.empty()) {
+                    Ticket *t = find_ticket(b, b->queue.front());
+                    if (!t || t->status != SW_TICKET_QUEUED) { b->queue.pop_front(); continue; }
+                    if (!t->swept) { classic_now.push_back(t); b->queue.pop_front(); continue; }
+                    const bool slots_full = b->cfg.max_slots > 0 && b->nresident >= b->cfg.max_slots;
+                    if (slots_full || b->resident + t->bytes > b->cfg.budget_bytes) break;
+                    t->edges = (double *)b->arena.alloc((size_t)t->geom.edge_doubles * sizeof(double));
+                    if (!t->edges) break;  // retry when memory frees up
+                    t->phase = 0;
+                    t->status = SW_TICKET_RUNNING;
+                    t->t_start = now_s();
+                    b->resident += t->bytes;
+                    b->nresident += 1;
+                    resident.push_back(t);
+                    b->queue.pop_front();
+                }
+                if (!resident.empty() || !classic_now.empty()) break;
+                if (b->stop) return;
+                b->cv.wait_for(lk, std::chrono::milliseconds(2));
+            }
+        }
+        for (Ticket *t : classic_now) {
+            (void)run_classic_ticket(*t, b->stream);
+            std::lock_guard<std::mutex> lk(b->mu);
+            b->cv.notify_all();
+        }
+        if (resident.empty()) continue;
+
+        // one tick: every resident solve advances one phase, one launch per group
+        std::map<std::pair<int, int>, std::vector<Ticket *>> groups;
+        for (Ticket *t : resident) groups[{t->prob.scheme, t->P}].push_back(t);
+        hipError_t e = hipSuccess;
+        for (auto &kv : groups) {
+            TickTables &tt = tables[kv.first];
+            tt.scheme = kv.first.first;
+            tt.P = kv.first.second;
+            if (tt.grid_cap <= 1) tt.grid_cap = batch_blocks_per_cu(tt.scheme, tt.P) * num_cus();
+            size_t ni = 0;
+            for (Ticket *t : kv.second) ni += (size_t)t->geom.K;
+            tt.ensure(kv.second.size(), ni);
+            size_t k = 0;
+            for (size_t s = 0; s < kv.second.size(); ++s) {
+                tt.h_desc[s] = make_desc(*kv.second[s]);
+                for (int64_t j = 0; j < kv.second[s]->geom.K; ++j) tt.h_items[k++] = make_int2((int)s, (int)j);
+            }
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(tt.d_desc, tt.h_desc, kv.second.size() * sizeof(SolveDesc),
+                                   hipMemcpyHostToDevice, b->stream);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(tt.d_items, tt.h_items, ni * sizeof(int2), hipMemcpyHostToDevice, b->stream);
+            if (e == hipSuccess)
+                e = launch_batch_phase(tt.scheme, tt.P, tt.d_desc, tt.d_items, (int64_t)ni, -1,
+                                       (int)std::min<int64_t>((int64_t)ni, tt.grid_cap), b->stream);
+        }
+        if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+        const double t_done = now_s();
+        {
+            std::lock_guard<std::mutex> lk(b->mu);
+            b->ticks += 1;
+            std::vector<Ticket *> still;
+            for (Ticket *t : resident) {
+                t->phase += 1;
+                const bool finished = t->phase >= phase_count(t->geom.Q, t->geom.rem);
+                if (e != hipSuccess || finished) {
+                    t->status = e == hipSuccess ? SW_TICKET_DONE : SW_TICKET_FAILED;
+                    t->t_end = t_done;
+                    b->arena.release(t->edges, (size_t)t->geom.edge_doubles * sizeof(double));
+                    t->edges = nullptr;
+                    b->resident -= t->bytes;
+                    b->nresident -= 1;
+                } else {
+                    still.push_back(t);
+                }
+            }
+            resident.swap(still);
+            if (e != hipSuccess) b->worker_error = hipGetErrorString(e);
+            b->cv.notify_all();
+        }
+    }
+}
+
+int serve_start(sw_batch *b)
+{
+    BHIP(hipGetDevice(&b->device));
+    BHIP(hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking));
+    b->worker = std::thread(serve_loop, b);
+    return SW_OK;
+}
+
+void serve_stop(sw_batch *b)
+{
+    {
+        std::lock_guard<std::mutex> lk(b->mu);
+        b->stop = true;
+        // queued tickets that never started are cancelled
+        for (uint64_t id : b->queue) {
+            Ticket *t = find_ticket(b, id);
+            if (t && t->status == SW_TICKET_QUEUED) t->status = SW_TICKET_CANCELLED;
+        }
+        b->queue.clear();
+        b->cv.notify_all();
+    }
+    if (b->worker.joinable()) b->worker.join();
+    if (b->stream) (void)hipStreamDestroy(b->stream);
+    b->stream = nullptr;
+}
+
+}  // namespace
 
 extern "C" {
 
 int batch_create(const sw_batch_config *config, sw_batch **out)
 {
     if (!config || !out) return fail(SW_EINVAL, "NULL argument");
-    if (config->budget_bytes <= 0 || config->max_slots < 0 || config->flags != 0)
+    if (config->budget_bytes <= 0 || config->max_slots < 0 || (config->flags & ~SW_BATCH_SERVE) != 0)
         return fail(SW_EINVAL, "invalid batch configuration");
     sw_batch *b = new (std::nothrow) sw_batch();
     if (!b) return fail(SW_ENOMEM, "batch allocation failed");
     b->cfg = *config;
+    b->serve = (config->flags & SW_BATCH_SERVE) != 0;
+    if (b->serve) {
+        int rc = serve_start(b);
+        if (rc) { delete b; return rc; }
+    }
     *out = b;
     return SW_OK;
 }
@@ -72,72 +535,95 @@ int batch_submit(sw_batch *b, const sw_problem *problem, double *d_state, uint64
     t.prob = *problem;
     t.state = d_state;
     t.bytes = bytes;
+    t.t_submit = now_s();
+    t.swept = batch_shape(*problem, &t.P, &t.geom) && problem->nsteps > 0;
     b->tickets.push_back(t);
     *ticket = t.id;
+    if (b->serve) {
+        b->queue.push_back(t.id);
+        b->cv.notify_all();
+    }
     return SW_OK;
 }
 
 int batch_run(sw_batch *b, void *hip_stream)
 {
     if (!b) return fail(SW_EINVAL, "NULL batch");
+    if (b->serve) return fail(SW_EINVAL, "batch_run is for ensemble batches; served batches run by themselves");
     std::lock_guard<std::mutex> lk(b->mu);
     hipStream_t st = (hipStream_t)hip_stream;
-    std::vector<Ticket *> running;
-    int64_t in_use = 0;
-    auto drain = [&]() -> int {
-        if (running.empty()) return SW_OK;
-        hipError_t e = hipStreamSynchronize(st);
-        for (Ticket *t : running) {
-            swept_plan_destroy(t->plan);
-            t->plan = nullptr;
-            t->status = e == hipSuccess ? SW_TICKET_DONE : SW_TICKET_FAILED;
+    int rc_all = SW_OK;
+    // admit queued tickets in submission order, in waves that fit the budget and slots
+    size_t i = 0;
+    while (i < b->tickets.size()) {
+        std::vector<Ticket *> wave;
+        int64_t used = 0;
+        for (; i < b->tickets.size(); ++i) {
+            Ticket &t = b->tickets[i];
+            if (t.status != SW_TICKET_QUEUED) continue;
+            if (!t.swept) {
+                if (t.prob.nsteps == 0) { t.status = SW_TICKET_DONE; t.t_start = t.t_end = now_s(); continue; }
+                int rc = run_classic_ticket(t, st);
+                if (rc && rc_all == SW_OK) rc_all = rc;
+                continue;
+            }
+            const bool slots_full = b->cfg.max_slots > 0 && (int)wave.size() >= b->cfg.max_slots;
+            if (!wave.empty() && (slots_full || used + t.bytes > b->cfg.budget_bytes)) break;
+            wave.push_back(&t);
+            used += t.bytes;
         }
-        running.clear();
-        in_use = 0;
-        return e == hipSuccess ? SW_OK : hip_fail(e, "batch solve");
-    };
-    for (Ticket &t : b->tickets) {
-        if (t.status != SW_TICKET_QUEUED) continue;
-        const bool slots_full = b->cfg.max_slots > 0 && (int)running.size() >= b->cfg.max_slots;
-        if (slots_full || in_use + t.bytes > b->cfg.budget_bytes) {
-            int rc = drain();
-            if (rc) return rc;
+        if (!wave.empty()) {
+            int rc = run_ensemble(b, wave, st);
+            if (rc && rc_all == SW_OK) rc_all = rc;
         }
-        int rc = swept_plan(&t.prob, nullptr, &t.plan);
-        if (rc) { t.status = SW_TICKET_FAILED; continue; }
-        t.status = SW_TICKET_RUNNING;
-        sw_plan_info info;
-        swept_plan_info(t.plan, &info);
-        rc = info.swept_ok ? swept_solve(t.plan, t.state, st) : classic_solve(t.plan, t.state, st);
-        if (rc) { t.status = SW_TICKET_FAILED; swept_plan_destroy(t.plan); t.plan = nullptr; continue; }
-        running.push_back(&t);
-        in_use += t.bytes;
     }
-    return drain();
+    return rc_all;
 }
 
 int batch_poll(sw_batch *b, uint64_t ticket, int32_t *status_out)
 {
     if (!b || !status_out) return fail(SW_EINVAL, "NULL argument");
     std::lock_guard<std::mutex> lk(b->mu);
-    for (const Ticket &t : b->tickets)
-        if (t.id == ticket) { *status_out = t.status; return SW_OK; }
-    return fail(SW_EINVAL, "unknown ticket");
+    Ticket *t = find_ticket(b, ticket);
+    if (!t) return fail(SW_EINVAL, "unknown ticket");
+    *status_out = t->status;
+    return SW_OK;
+}
+
+int batch_ticket_info(sw_batch *b, uint64_t ticket, sw_ticket_info *out)
+{
+    if (!b || !out) return fail(SW_EINVAL, "NULL argument");
+    std::lock_guard<std::mutex> lk(b->mu);
+    Ticket *t = find_ticket(b, ticket);
+    if (!t) return fail(SW_EINVAL, "unknown ticket");
+    sw_ticket_info i;
+    std::memset(&i, 0, sizeof(i));
+    i.status = t->status;
+    i.swept = t->swept ? 1 : 0;
+    i.width = t->swept ? t->geom.w : 0;
+    i.phases = t->swept ? phase_count(t->geom.Q, t->geom.rem) : 0;
+    i.submit_s = t->t_submit;
+    i.start_s = t->t_start;
+    i.end_s = t->t_end;
+    *out = i;
+    return SW_OK;
 }
 
 int batch_wait(sw_batch *b, uint64_t ticket, int64_t timeout_us)
 {
-    const auto t0 = std::chrono::steady_clock::now();
+    if (!b) return fail(SW_EINVAL, "NULL batch");
+    const auto t0 = Clock::now();
+    std::unique_lock<std::mutex> lk(b->mu);
     for (;;) {
-        int32_t s = 0;
-        int rc = batch_poll(b, ticket, &s);
-        if (rc) return rc;
-        if (s == SW_TICKET_DONE || s == SW_TICKET_CANCELLED) return SW_OK;
-        if (s == SW_TICKET_FAILED) return fail(SW_EDEVICE, "ticket failed");
-        const auto us = std::chrono::duration_cast<std::chrono::microseconds>(
-                            std::chrono::steady_clock::now() - t0).count();
-        if (timeout_us >= 0 && us >= timeout_us) return fail(SW_ENOTREADY, "ticket not finished");
-        std::this_thread::sleep_for(std::chrono::microseconds(50));
+        Ticket *t = find_ticket(b, ticket);
+        if (!t) return fail(SW_EINVAL, "unknown ticket");
+        if (t->status == SW_TICKET_DONE || t->status == SW_TICKET_CANCELLED) return SW_OK;
+        if (t->status == SW_TICKET_FAILED) return fail(SW_EDEVICE, "ticket failed");
+        if (!b->serve && t->status == SW_TICKET_QUEUED)
+            return fail(SW_ENOTREADY, "ticket is queued; call batch_run");
+        const auto waited = std::chrono::duration_cast<std::chrono::microseconds>(Clock::now() - t0).count();
+        if (timeout_us >= 0 && waited >= timeout_us) return fail(SW_ENOTREADY, "ticket not finished");
+        b->cv.wait_for(lk, std::chrono::microseconds(200));
     }
 }
 
@@ -145,20 +631,25 @@ int batch_cancel(sw_batch *b, uint64_t ticket)
 {
     if (!b) return fail(SW_EINVAL, "NULL batch");
     std::lock_guard<std::mutex> lk(b->mu);
-    for (Ticket &t : b->tickets)
-        if (t.id == ticket) {
-            if (t.status == SW_TICKET_QUEUED) { t.status = SW_TICKET_CANCELLED; return SW_OK; }
-            return fail(SW_EBUSY, "ticket already started");
-        }
-    return fail(SW_EINVAL, "unknown ticket");
+    Ticket *t = find_ticket(b, ticket);
+    if (!t) return fail(SW_EINVAL, "unknown ticket");
+    if (t->status != SW_TICKET_QUEUED) return fail(SW_EBUSY, "ticket already started");
+    t->status = SW_TICKET_CANCELLED;
+    if (b->serve) {
+        auto it = std::find(b->queue.begin(), b->queue.end(), ticket);
+        if (it != b->queue.end()) b->queue.erase(it);
+    }
+    b->cv.notify_all();
+    return SW_OK;
 }
 
 void batch_destroy(sw_batch *b)
 {
     if (!b) return;
+    if (b->serve) serve_stop(b);
     {
         std::lock_guard<std::mutex> lk(b->mu);
-        for (Ticket &t : b->tickets) swept_plan_destroy(t.plan);
+        b->arena.destroy();
     }
     delete b;
 }

@@ -49,17 +49,20 @@ __device__ __forceinline__ void level_step(const TileArgs &a, int g, int NW, int
     constexpr int NV = Sch::NV, R = Sch::R;
     const int lane = g & 63, wave = g >> 6, buf = s & 1;
     if (MULTI) {
-        if (lane == 0) {
+        // publish this wave's first and last R points (wave positions p = lane P + k)
+        if (lane * P < R) {
 #pragma unroll
             for (int v = 0; v < NV; ++v)
 #pragma unroll
-                for (int i = 0; i < R; ++i) xch[buf][wave][0][v][i] = src[v][i];
+                for (int k = 0; k < P; ++k)
+                    if (lane * P + k < R) xch[buf][wave][0][v][lane * P + k] = src[v][k];
         }
-        if (lane == 63) {
+        if (lane * P + P > 64 * P - R) {
 #pragma unroll
             for (int v = 0; v < NV; ++v)
 #pragma unroll
-                for (int i = 0; i < R; ++i) xch[buf][wave][1][v][i] = src[v][P - R + i];
+                for (int k = 0; k < P; ++k)
+                    if (lane * P + k >= 64 * P - R) xch[buf][wave][1][v][lane * P + k - (64 * P - R)] = src[v][k];
         }
         __syncthreads();
     }
@@ -71,59 +74,77 @@ __device__ __forceinline__ void level_step(const TileArgs &a, int g, int NW, int
     element_lane_span(P, R, INC, SMOD, lo, hi, base, lmin, lmax);
     if (!(lmin < 64 && lmax > 0 && lmin < lmax)) return;
 
+    // ext[v][i] holds tile position g P - R + i, ext[v][R + P + i] position g P + P + i.
+    static_assert(P >= R || P == 1, "a lane's halo spans at most its neighbours, or one point per lane");
     double ext[NV][P + 2 * R];
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
 #pragma unroll
         for (int k = 0; k < P; ++k) ext[v][R + k] = src[v][k];
+        if constexpr (P >= R) {
 #pragma unroll
-        for (int i = 0; i < R; ++i) {
-            ext[v][i] = dpp_zero<DPP_WAVE_SHR1>(src[v][P - R + i]);
-            ext[v][R + P + i] = dpp_zero<DPP_WAVE_SHL1>(src[v][i]);
+            for (int i = 0; i < R; ++i) {
+                ext[v][i] = dpp_zero<DPP_WAVE_SHR1>(src[v][P - R + i]);
+                ext[v][R + P + i] = dpp_zero<DPP_WAVE_SHL1>(src[v][i]);
+            }
+        } else {  // one point per lane: points further away pass through successive lanes
+            ext[v][R - 1] = dpp_zero<DPP_WAVE_SHR1>(src[v][0]);
+#pragma unroll
+            for (int i = R - 2; i >= 0; --i) ext[v][i] = dpp_zero<DPP_WAVE_SHR1>(ext[v][i + 1]);
+            ext[v][R + 1] = dpp_zero<DPP_WAVE_SHL1>(src[v][0]);
+#pragma unroll
+            for (int i = 1; i < R; ++i) ext[v][R + 1 + i] = dpp_zero<DPP_WAVE_SHL1>(ext[v][R + i]);
         }
     }
+    const int x0 = g * P;  // first tile position of this lane
     // The tile's outer halo is read by the widest level of a Diamond/Down only.
     if (s == a.H && a.kind != PH_UP) {
-        if (g == 0) {
+        if (x0 < R) {
 #pragma unroll
             for (int v = 0; v < NV; ++v)
 #pragma unroll
-                for (int i = 0; i < R; ++i) ext[v][i] = hl[v][i];
+                for (int i = 0; i < R; ++i)
+                    if (x0 - R + i < 0) ext[v][i] = hl[v][x0 + i];
         }
-        if (g == 64 * NW - 1) {
+        if (x0 + P + R > a.w) {
 #pragma unroll
             for (int v = 0; v < NV; ++v)
 #pragma unroll
-                for (int i = 0; i < R; ++i) ext[v][R + P + i] = hr[v][i];
+                for (int i = 0; i < R; ++i)
+                    if (x0 + P + i >= a.w) ext[v][R + P + i] = hr[v][x0 + P + i - a.w];
         }
     }
     if (MULTI) {
-        if (lane == 0 && wave > 0) {
+        if (lane * P < R && wave > 0) {
 #pragma unroll
             for (int v = 0; v < NV; ++v)
 #pragma unroll
-                for (int i = 0; i < R; ++i) ext[v][i] = xch[buf][wave - 1][1][v][i];
+                for (int i = 0; i < R; ++i)
+                    if (lane * P - R + i < 0) ext[v][i] = xch[buf][wave - 1][1][v][lane * P + i];
         }
-        if (lane == 63 && wave < NW - 1) {
+        if (lane * P + P + R > 64 * P && wave < NW - 1) {
 #pragma unroll
             for (int v = 0; v < NV; ++v)
 #pragma unroll
-                for (int i = 0; i < R; ++i) ext[v][R + P + i] = xch[buf][wave + 1][0][v][i];
+                for (int i = 0; i < R; ++i)
+                    if (lane * P + P + i >= 64 * P)
+                        ext[v][R + P + i] = xch[buf][wave + 1][0][v][lane * P + P + i - 64 * P];
         }
     }
-    if (WALL) {
-        const int gw = a.w / (2 * P) - 1;  // last lane left of the wall
-        if (g == gw) {
+    if (WALL) {  // Dirichlet wall at the tile centre: across it lie the ghost values
+        if (x0 >= half && x0 - R < half) {
 #pragma unroll
             for (int v = 0; v < NV; ++v)
 #pragma unroll
-                for (int i = 0; i < R; ++i) ext[v][R + P + i] = a.c.ghost_r[v];
+                for (int i = 0; i < R; ++i)
+                    if (x0 - R + i < half) ext[v][i] = a.c.ghost_l[v];
         }
-        if (g == gw + 1) {
+        if (x0 < half && x0 + P + R > half) {
 #pragma unroll
             for (int v = 0; v < NV; ++v)
 #pragma unroll
-                for (int i = 0; i < R; ++i) ext[v][i] = a.c.ghost_l[v];
+                for (int i = 0; i < R; ++i)
+                    if (x0 + P + i >= half) ext[v][R + P + i] = a.c.ghost_r[v];
         }
     }
     bool in[P];
@@ -194,14 +215,12 @@ __device__ __forceinline__ void run_levels(const TileArgs &a, int g, int NW, dou
     }
 }
 
-template <class Sch, int P, int MAXT>
-__global__ __launch_bounds__(MAXT) void swept_tile(TileArgs a)
+// One tile of one phase: load the two rows, run the phase's levels, store.
+template <class Sch, int P>
+__device__ __forceinline__ void tile_body(const TileArgs &a, int64_t j, int g, int NW,
+                                          double (*xch)[16][2][Sch::NV][Sch::R])
 {
     constexpr int NV = Sch::NV, R = Sch::R;
-    __shared__ double xch[2][16][2][NV][R];
-    const int g = threadIdx.x;
-    const int NW = blockDim.x >> 6;
-    const int64_t j = blockIdx.x;
     double r0[NV][P], r1[NV][P], hl[NV][R], hr[NV][R];
     lane_load<Sch, P>(a, j, g, r0, r1, hl, hr);
     const bool wall = straddles_wall(a, j);
@@ -214,6 +233,44 @@ __global__ __launch_bounds__(MAXT) void swept_tile(TileArgs a)
         else run_levels<Sch, P, false, false>(a, g, NW, r0, r1, hl, hr, xch);
     }
     lane_store<Sch, P>(a, j, g, r0, r1);
+}
+
+template <class Sch, int P, int MAXT>
+__global__ __launch_bounds__(MAXT) void swept_tile(TileArgs a)
+{
+    __shared__ double xch[2][16][2][Sch::NV][Sch::R];
+    tile_body<Sch, P>(a, (int64_t)blockIdx.x, (int)threadIdx.x, (int)(blockDim.x >> 6), xch);
+}
+
+// Batched phase: every work item is (solve, tile) of one of many independent
+// solves; one-wave work-groups stride over the items, so a launch covers the
+// current phase of every solve in the batch.  `global_phase` >= 0 runs that
+// phase for every solve; -1 takes each solve's own phase (served batches).
+template <class Sch, int P>
+__global__ __launch_bounds__(64) void batch_tiles(const SolveDesc *__restrict__ desc,
+                                                  const int2 *__restrict__ items, int64_t nitems,
+                                                  int global_phase)
+{
+    __shared__ double xch[2][16][2][Sch::NV][Sch::R];
+    for (int64_t i = blockIdx.x; i < nitems; i += gridDim.x) {
+        const int2 it = items[i];
+        const SolveDesc &d = desc[it.x];
+        const int p = global_phase >= 0 ? global_phase : d.phase;
+        if (p >= d.nphases) continue;
+        TileArgs a;
+        a.state = d.state;
+        a.edges = d.edges;
+        a.n = d.n;
+        a.K = d.K;
+        a.w = d.w;
+        a.H = d.H;
+        a.E = d.E;
+        a.dirichlet = d.dirichlet;
+        a.pad = 0;
+        a.c = d.c;
+        phase_at(d.Q, d.rem, d.H, p, a.kind, a.levels, a.offset);
+        tile_body<Sch, P>(a, (int64_t)it.y, (int)threadIdx.x, 1, xch);
+    }
 }
 
 // Classic: one thread per point, one launch per sub-step (Sec. 4.1).  For the
@@ -250,6 +307,11 @@ __global__ __launch_bounds__(256) void classic_level(const double *__restrict__ 
     for (int v = 0; v < NV; ++v) dst[(int64_t)v * n + i] = out[v][0];
 }
 
+__global__ void stamp_kernel(uint64_t *stamps, int idx)
+{
+    if (threadIdx.x == 0) stamps[idx] = wall_clock64();
+}
+
 // Flag non-finite values (optional post-solve check).
 __global__ void nonfinite_scan(const double *x, int64_t count, int *flag)
 {
@@ -271,7 +333,7 @@ template <class Sch>
 hipError_t launch_tile_p(const TileArgs &a, int P, int threads, hipStream_t st)
 {
     switch (P) {
-    case 1: if constexpr (Sch::R <= 1) return launch_tile<Sch, 1>(a, threads, st); break;
+    case 1: return launch_tile<Sch, 1>(a, threads, st);
     case 2: return launch_tile<Sch, 2>(a, threads, st);
     case 4: return launch_tile<Sch, 4>(a, threads, st);
     case 8: return launch_tile<Sch, 8>(a, threads, st);
@@ -302,6 +364,77 @@ hipError_t launch_classic_level(int scheme, const double *src, double *dst, int6
         hipLaunchKernelGGL(classic_level<KS>, dim3(blocks), dim3(T), 0, st, src, dst, n, dirichlet, predictor, c);
     else
         hipLaunchKernelGGL(classic_level<Euler>, dim3(blocks), dim3(T), 0, st, src, dst, n, dirichlet, predictor, c);
+    return hipGetLastError();
+}
+
+namespace {
+
+template <class Sch, int P>
+hipError_t batch_launch_t(const SolveDesc *desc, const int2 *items, int64_t nitems, int global_phase,
+                          int grid, hipStream_t st)
+{
+    hipLaunchKernelGGL((batch_tiles<Sch, P>), dim3((unsigned)grid), dim3(64), 0, st, desc, items, nitems,
+                       global_phase);
+    return hipGetLastError();
+}
+
+template <class Sch, int P>
+int batch_occupancy_t()
+{
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_tiles<Sch, P>, 64, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        return 1;
+    }
+    return n > 0 ? n : 1;
+}
+
+template <class Sch>
+hipError_t batch_launch_s(int P, const SolveDesc *desc, const int2 *items, int64_t nitems, int global_phase,
+                          int grid, hipStream_t st)
+{
+    switch (P) {
+    case 1: return batch_launch_t<Sch, 1>(desc, items, nitems, global_phase, grid, st);
+    case 2: return batch_launch_t<Sch, 2>(desc, items, nitems, global_phase, grid, st);
+    case 4: return batch_launch_t<Sch, 4>(desc, items, nitems, global_phase, grid, st);
+    case 8: return batch_launch_t<Sch, 8>(desc, items, nitems, global_phase, grid, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <class Sch>
+int batch_occupancy_s(int P)
+{
+    switch (P) {
+    case 1: return batch_occupancy_t<Sch, 1>();
+    case 2: return batch_occupancy_t<Sch, 2>();
+    case 4: return batch_occupancy_t<Sch, 4>();
+    case 8: return batch_occupancy_t<Sch, 8>();
+    default: return 1;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_batch_phase(int scheme, int P, const SolveDesc *desc, const int2 *items, int64_t nitems,
+                              int global_phase, int grid, hipStream_t st)
+{
+    if (nitems <= 0) return hipSuccess;
+    if (scheme == 0) return batch_launch_s<Heat>(P, desc, items, nitems, global_phase, grid, st);
+    if (scheme == 1) return batch_launch_s<KS>(P, desc, items, nitems, global_phase, grid, st);
+    return batch_launch_s<Euler>(P, desc, items, nitems, global_phase, grid, st);
+}
+
+int batch_blocks_per_cu(int scheme, int P)
+{
+    if (scheme == 0) return batch_occupancy_s<Heat>(P);
+    if (scheme == 1) return batch_occupancy_s<KS>(P);
+    return batch_occupancy_s<Euler>(P);
+}
+
+hipError_t launch_stamp(uint64_t *stamps, int idx, hipStream_t st)
+{
+    hipLaunchKernelGGL(stamp_kernel, dim3(1), dim3(64), 0, st, stamps, idx);
     return hipGetLastError();
 }
 

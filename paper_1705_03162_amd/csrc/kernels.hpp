@@ -14,6 +14,18 @@ hipError_t launch_swept_phase(int scheme, int P, int threads, const TileArgs &a,
 hipError_t launch_classic_level(int scheme, const double *src, double *dst, int64_t n, int dirichlet,
                                 int predictor, const Consts &c, hipStream_t st);
 
+// One phase of many independent solves: items[i] = (solve index into desc, tile).
+// global_phase >= 0 runs that phase for every solve, -1 each solve's own phase.
+// `grid` one-wave work-groups stride over the items.
+hipError_t launch_batch_phase(int scheme, int P, const SolveDesc *desc, const int2 *items, int64_t nitems,
+                              int global_phase, int grid, hipStream_t st);
+
+// Writes the device wall clock (constant-rate counter) to stamps[idx].
+hipError_t launch_stamp(uint64_t *stamps, int idx, hipStream_t st);
+
+// Resident one-wave batch work-groups per CU for (scheme, P).
+int batch_blocks_per_cu(int scheme, int P);
+
 // Sets *flag to 1 if any of x[0..count) is not finite (flag must be zeroed first).
 hipError_t launch_nonfinite_scan(const double *x, int64_t count, int *flag, hipStream_t st);
 

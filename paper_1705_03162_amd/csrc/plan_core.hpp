@@ -41,7 +41,6 @@ inline int scheme_nvars(int scheme) { return scheme == SW_EULER ? 3 : 1; }
 inline bool legal_points_per_lane(int scheme, int P)
 {
     if (P != 1 && P != 2 && P != 4 && P != 8 && P != 16) return false;
-    if (P < scheme_radius(scheme)) return false;      // a lane's halo comes from one neighbour
     if (scheme == SW_EULER && P > 8) return false;    // register budget of the flux stencil
     return true;
 }
@@ -131,14 +130,12 @@ inline std::vector<Phase> build_phases(const Geom &g)
 {
     std::vector<Phase> ph;
     if (g.levels == 0) return ph;
-    if (g.Q >= 1) {
-        ph.push_back({PH_UP, g.H, 0});
-        for (int64_t q = 1; q < g.Q; ++q) ph.push_back({PH_DIAMOND, 2 * g.H - 1, (int32_t)(q & 1)});
-        ph.push_back({PH_DOWN, g.H, (int32_t)(g.Q & 1)});
-    }
-    if (g.rem > 0) {
-        ph.push_back({PH_UP, (int32_t)g.rem, 0});
-        ph.push_back({PH_DOWN, (int32_t)g.rem, 1});
+    const int cnt = phase_count(g.Q, g.rem);
+    ph.reserve((size_t)cnt);
+    for (int p = 0; p < cnt; ++p) {
+        Phase x;
+        phase_at(g.Q, g.rem, g.H, p, x.kind, x.levels, x.offset);
+        ph.push_back(x);
     }
     return ph;
 }

@@ -54,6 +54,17 @@ struct TileArgs {
     Consts c;
 };
 
+// One solve inside a batch: its buffers, geometry and current phase.
+struct SolveDesc {
+    double *state;
+    double *edges;
+    int64_t n, K, Q, rem;
+    int32_t w, H, E, dirichlet;
+    int32_t nphases;   // phase_count(Q, rem)
+    int32_t phase;     // next phase to run (served batches advance solves independently)
+    Consts c;
+};
+
 SW_HD int64_t tile_start(const TileArgs &a, int64_t j) { return j * a.w + (a.offset ? a.w / 2 : 0); }
 SW_HD int64_t wrap_once(int64_t x, int64_t n) { return x >= n ? x - n : x; }
 SW_HD int64_t slot_a(const TileArgs &a, int64_t j)
@@ -68,6 +79,25 @@ SW_HD int64_t slot_b(const TileArgs &a, int64_t j)
 }
 template <class Sch>
 SW_HD int64_t slot_base(const TileArgs &a, int64_t s) { return s * (int64_t)Sch::NV * 2 * a.E; }
+
+// Phase p of a solve with Q full phases of H levels and a remainder of rem
+// levels: Up(H), Diamond x (Q-1) at offsets 1, 0, 1, ..., Down(H) at offset
+// Q mod 2, then Up(rem), Down(rem) at offsets 0, 1 (Sec. 3.2's zig-zag).
+SW_HD int phase_count(int64_t Q, int64_t rem) { return (int)((Q >= 1 ? Q + 1 : 0) + (rem > 0 ? 2 : 0)); }
+SW_HD void phase_at(int64_t Q, int64_t rem, int H, int64_t p, int32_t &kind, int32_t &levels,
+                    int32_t &offset)
+{
+    if (Q >= 1 && p <= Q) {
+        if (p == 0) { kind = PH_UP; levels = H; offset = 0; }
+        else if (p < Q) { kind = PH_DIAMOND; levels = 2 * H - 1; offset = (int32_t)(p & 1); }
+        else { kind = PH_DOWN; levels = H; offset = (int32_t)(Q & 1); }
+        return;
+    }
+    const int64_t q = p - (Q >= 1 ? Q + 1 : 0);  // 0: remainder Up, 1: remainder Down
+    kind = q == 0 ? PH_UP : PH_DOWN;
+    levels = (int32_t)rem;
+    offset = q == 0 ? 0 : 1;
+}
 
 // Number of levels a tile computes in this launch.
 SW_HD int tile_levels(const TileArgs &a)

@@ -24,9 +24,6 @@ WAVES = (1, 2, 4, 8, 16)
 
 
 def legal(scheme: int, P: int, threads: int) -> bool:
-    r = 1 if scheme == 0 else 2
-    if P < r:
-        return False
     if scheme == 2 and P > 8:
         return False
     max_t = (256 if P >= 8 else 512) if scheme == 2 else (512 if P >= 16 else 1024)

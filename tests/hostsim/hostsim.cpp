@@ -31,7 +31,6 @@ void run_phase(const Geom &g, const TileArgs &a)
         for (int l = 0; l < lanes; ++l) lane_load<Sch, P>(a, j, l, L[l].r0, L[l].r1, L[l].hl, L[l].hr);
         const int nlev = tile_levels(a);
         const bool wall = straddles_wall(a, j);
-        const int gw = a.w / (2 * P) - 1;
         for (int s = 1; s <= nlev; ++s) {
             const bool odd = (s & 1) != 0;
             // like the kernel: the points just outside the tile are supplied only at the
@@ -44,15 +43,16 @@ void run_phase(const Geom &g, const TileArgs &a)
                 for (int v = 0; v < NV; ++v) {
                     for (int k = 0; k < P; ++k) ext[v][R + k] = src[v][k];
                     for (int i = 0; i < R; ++i) {
-                        ext[v][i] = l > 0 ? (odd ? L[l - 1].r0 : L[l - 1].r1)[v][P - R + i]
-                                          : (outer ? L[0].hl[v][i] : 0.0);
-                        ext[v][R + P + i] = l < lanes - 1 ? (odd ? L[l + 1].r0 : L[l + 1].r1)[v][i]
-                                                          : (outer ? L[lanes - 1].hr[v][i] : 0.0);
+                        // halo points by position: q < 0 / q >= w lie outside the tile
+                        const int ql = l * P - R + i, qr = l * P + P + i;
+                        ext[v][i] = ql >= 0 ? (odd ? L[ql / P].r0 : L[ql / P].r1)[v][ql % P]
+                                            : (outer ? L[0].hl[v][ql + R] : 0.0);
+                        ext[v][R + P + i] = qr < a.w ? (odd ? L[qr / P].r0 : L[qr / P].r1)[v][qr % P]
+                                                     : (outer ? L[0].hr[v][qr - a.w] : 0.0);
+                        // Dirichlet wall at the tile centre: across it lie the ghosts
+                        if (wall && l * P >= a.w / 2 && ql < a.w / 2) ext[v][i] = a.c.ghost_l[v];
+                        if (wall && l * P < a.w / 2 && qr >= a.w / 2) ext[v][R + P + i] = a.c.ghost_r[v];
                     }
-                    if (wall && l == gw)
-                        for (int i = 0; i < R; ++i) ext[v][R + P + i] = a.c.ghost_r[v];
-                    if (wall && l == gw + 1)
-                        for (int i = 0; i < R; ++i) ext[v][i] = a.c.ghost_l[v];
                 }
                 // element masks exactly as the kernel derives them (residues from s mod G)
                 const int m = half_width(a, s);

@@ -1,0 +1,132 @@
+"""Batched and served solves on the GPU: each result equals the same problem
+solved alone (swept_solve), bit for bit, and the oracle within 1e-12."""
+import threading
+import time
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+torch = pytest.importorskip("torch")
+import paper_1705_03162_amd as sw  # noqa: E402
+from paper_1705_03162_amd import _native as N  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def alone(prob, ic):
+    with sw.Plan(prob) as plan:
+        x = torch.tensor(ic, dtype=torch.float64, device=DEV)
+        if plan.info()["swept_ok"]:
+            plan.swept(x)
+        else:
+            plan.classic(x)
+        torch.cuda.synchronize()
+    return x.cpu().numpy()
+
+
+def mixed_problems(count, seed, schemes=(W.HEAT, W.KS), nmax=8192, smax=900):
+    rng = np.random.default_rng(seed)
+    out = []
+    for j in range(count):
+        scheme = schemes[int(rng.integers(0, len(schemes)))]
+        n = 64 * int(rng.integers(1, nmax // 64 + 1))
+        steps = int(rng.integers(1, smax))
+        if scheme == W.HEAT:
+            prob, ic = W.heat_problem(n, steps), W.fourier_ic(n, seed=j)
+        elif scheme == W.KS:
+            prob, ic = W.ks_problem(n, steps), W.fourier_ic(n, seed=j)
+        else:
+            prob, ic = W.sod_problem(n, steps), W.sod_ic(n)
+        out.append((prob, ic))
+    return out
+
+
+def test_ensemble_each_result_equals_alone(oracle_mod):
+    probs = mixed_problems(48, seed=1)
+    probs.append((W.heat_problem(1000, 77), W.fourier_ic(1000, 5)))   # no swept width: classic
+    probs.append((W.ks_problem(4096, 0), W.fourier_ic(4096, 6)))      # zero steps
+    print(f"[gpu] ensemble of {len(probs)} solves", flush=True)
+    states = [torch.tensor(ic, dtype=torch.float64, device=DEV) for _, ic in probs]
+    with sw.Batch(budget_bytes=1 << 34) as b:
+        tickets = [b.submit(p, x) for (p, _), x in zip(probs, states)]
+        b.run()
+        for t in tickets:
+            assert b.poll(t) == N.SW_TICKET_DONE
+        infos = [b.info(t) for t in tickets]
+    torch.cuda.synchronize()
+    assert infos[-2]["swept"] == 0
+    for (prob, ic), x in zip(probs, states):
+        assert np.array_equal(x.cpu().numpy(), alone(prob, ic))
+    for prob, ic in probs[:6]:
+        got = alone(prob, ic)
+        want = oracle_mod.solve(prob, ic)
+        assert np.abs(got - want).max() <= 1e-12 * max(1.0, np.abs(want).max())
+
+
+def test_ensemble_with_euler_and_budget_waves():
+    probs = mixed_problems(20, seed=2, schemes=(W.HEAT, W.KS, W.EULER), nmax=4096, smax=400)
+    budget = max(3 * p.n * p.nvars * 8 for p, _ in probs) * 3   # a few solves per wave
+    states = [torch.tensor(ic, dtype=torch.float64, device=DEV) for _, ic in probs]
+    with sw.Batch(budget_bytes=budget, max_slots=5) as b:
+        tickets = [b.submit(p, x) for (p, _), x in zip(probs, states)]
+        b.run()
+        assert all(b.poll(t) == N.SW_TICKET_DONE for t in tickets)
+    for (prob, ic), x in zip(probs, states):
+        assert np.array_equal(x.cpu().numpy(), alone(prob, ic))
+
+
+def test_served_mix_equals_alone():
+    """Continuous batching: solves arrive while others run; each result is the
+    same as alone."""
+    probs = mixed_problems(30, seed=3, schemes=(W.HEAT, W.KS, W.EULER), nmax=4096, smax=600)
+    states = [torch.tensor(ic, dtype=torch.float64, device=DEV) for _, ic in probs]
+    torch.cuda.synchronize()
+    tickets = []
+    with sw.Batch(budget_bytes=1 << 33, max_slots=8, serve=True) as b:
+        def producer():
+            for (p, _), x in zip(probs, states):
+                tickets.append(b.submit(p, x))
+                time.sleep(0.002)
+        th = threading.Thread(target=producer)
+        th.start()
+        th.join()
+        for t in tickets:
+            b.wait(t, timeout_us=60_000_000)
+        infos = [b.info(t) for t in tickets]
+    assert all(i["status"] == N.SW_TICKET_DONE for i in infos)
+    assert all(i["end_s"] >= i["start_s"] >= i["submit_s"] for i in infos)
+    for (prob, ic), x in zip(probs, states):
+        assert np.array_equal(x.cpu().numpy(), alone(prob, ic))
+
+
+def test_served_budget_queues_and_cancel():
+    big = (W.ks_problem(1 << 16, 3000), W.fourier_ic(1 << 16, 1))
+    small = [(W.heat_problem(1024, 200 + j), W.fourier_ic(1024, j)) for j in range(4)]
+    budget = 3 * big[0].n * 8 + 10    # the big solve alone fills the budget
+    xs = [torch.tensor(ic, dtype=torch.float64, device=DEV) for _, ic in [big] + small]
+    with sw.Batch(budget_bytes=budget, serve=True) as b:
+        tb = b.submit(big[0], xs[0])
+        ts = [b.submit(p, x) for (p, _), x in zip(small, xs[1:])]
+        b.cancel(ts[1])               # still queued behind the big solve
+        assert b.poll(ts[1]) == N.SW_TICKET_CANCELLED
+        for t in [tb] + ts:
+            b.wait(t, timeout_us=60_000_000)
+        assert b.poll(tb) == N.SW_TICKET_DONE
+        for j, t in enumerate(ts):
+            assert b.poll(t) == (N.SW_TICKET_CANCELLED if j == 1 else N.SW_TICKET_DONE)
+    for j, ((prob, ic), x) in enumerate(zip([big] + small, xs)):
+        if j == 2:
+            assert np.array_equal(x.cpu().numpy(), ic)   # cancelled: untouched
+        else:
+            assert np.array_equal(x.cpu().numpy(), alone(prob, ic))
+
+
+def test_oversized_solve_rejected():
+    with sw.Batch(budget_bytes=1 << 20) as b:
+        x = torch.zeros((1, 1 << 16), dtype=torch.float64, device=DEV)
+        with pytest.raises(sw.SweptError) as e:
+            b.submit(W.heat_problem(1 << 16, 10), x)
+        assert e.value.status == N.SW_EBUSY

@@ -57,6 +57,11 @@ SMALL = [  # (problem factory, width, threads)
     (lambda: (W.sod_problem(1024, 500), W.sod_ic(1024)), 256, 64),
     (lambda: (W.sod_problem(2048, 901), W.sod_ic(2048)), 512, 128),
     (lambda: (W.sod_problem(4096, 64), W.sod_ic(4096)), 512, 64),
+    # one point per lane (P = 1 < r = 2): halos pass through two lanes
+    (lambda: (W.ks_problem(320, 301), W.fourier_ic(320, 11)), 64, 64),
+    (lambda: (W.ks_problem(1024, 257), W.fourier_ic(1024, 12)), 256, 256),
+    (lambda: (W.sod_problem(448, 350), W.sod_ic(448)), 64, 64),
+    (lambda: (W.sod_problem(1024, 200), W.sod_ic(1024)), 128, 128),
 ]
 
 

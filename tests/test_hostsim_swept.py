@@ -88,6 +88,9 @@ KS_CASES = [
     (1024, 250, 256, 128),
     (1024, 3, 1024, 64),      # P = 16, fewer levels than a phase
     (2048, 700, 1024, 512),
+    (64, 45, 64, 64),         # one point per lane (P = 1 < r = 2), K = 1
+    (320, 77, 64, 64),        # N = 64 * 5: only w = 64 divides it
+    (1024, 130, 256, 256),    # P = 1 across four waves
 ]
 
 
@@ -108,6 +111,8 @@ EULER_CASES = [
     (1024, 300, 512, 64),     # P = 8
     (1024, 201, 256, 128),
     (2048, 10, 512, 128),
+    (448, 90, 64, 64),        # P = 1, N = 64 * 7
+    (1024, 75, 128, 128),     # P = 1 across two waves
 ]
 
 
