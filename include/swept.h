@@ -58,6 +58,8 @@ extern "C" {
 
 #define SW_PERIODIC   0      /* stencil wraps around the ends (Appendix C) */
 #define SW_DIRICHLET  1      /* r ghost points per end held at bc_left / bc_right at every level */
+#define SW_REFLECTIVE 2      /* insulated ends, heat only (Appendix B, Eq. heatcond):
+                                T_{-1} = T_1, T_n = T_{n-2} for points 0..n-1 */
 
 /* sw_problem.flags */
 #define SW_PROBLEM_LIMITER_RECIPROCAL 1u  /* Euler: take the limiter ratio backward/forward
@@ -66,7 +68,7 @@ extern "C" {
 
 typedef struct {
     int32_t scheme;        /* SW_HEAT, SW_KS or SW_EULER */
-    int32_t bc;            /* SW_PERIODIC or SW_DIRICHLET */
+    int32_t bc;            /* SW_PERIODIC, SW_DIRICHLET or SW_REFLECTIVE */
     int64_t n;             /* grid points (heat, KS) or cells (Euler), >= 1 */
     int64_t nsteps;        /* full timesteps, >= 0 (0 = no-op) */
     double  dt, dx;        /* > 0 */

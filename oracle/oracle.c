@@ -32,6 +32,11 @@ static double at(const oracle_problem *p, const double *a, int64_t j, int v)
         if (k < 0) k += n;
         return a[(int64_t)v * n + k];
     }
+    if (p->bc == ORACLE_REFLECTIVE) {
+        /* insulated ends, Eq. heatcond: T_{-1} = T_1 and, for points 0..n-1, T_n = T_{n-2}
+           (mirror images about the end points) */
+        return j < 0 ? a[(int64_t)v * n - j] : a[(int64_t)v * n + 2 * (n - 1) - j];
+    }
     return j < 0 ? p->bc_left[v] : p->bc_right[v];
 }
 
@@ -198,7 +203,8 @@ static int valid(const oracle_problem *p)
 {
     if (!p) return 0;
     if (p->scheme < ORACLE_HEAT || p->scheme > ORACLE_EULER) return 0;
-    if (p->bc != ORACLE_PERIODIC && p->bc != ORACLE_DIRICHLET) return 0;
+    if (p->bc != ORACLE_PERIODIC && p->bc != ORACLE_DIRICHLET && p->bc != ORACLE_REFLECTIVE) return 0;
+    if (p->bc == ORACLE_REFLECTIVE && (p->scheme != ORACLE_HEAT || p->n < 2)) return 0;
     if (p->n < 1 || p->nsteps < 0) return 0;
     if (!(p->dt > 0.0) || !(p->dx > 0.0)) return 0;
     return 1;

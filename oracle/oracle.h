@@ -24,11 +24,12 @@ extern "C" {
 #endif
 
 enum { ORACLE_HEAT = 0, ORACLE_KS = 1, ORACLE_EULER = 2 };
-enum { ORACLE_PERIODIC = 0, ORACLE_DIRICHLET = 1 };
+enum { ORACLE_PERIODIC = 0, ORACLE_DIRICHLET = 1, ORACLE_REFLECTIVE = 2 };
 
 typedef struct {
     int32_t scheme;      /* ORACLE_HEAT, ORACLE_KS, ORACLE_EULER */
-    int32_t bc;          /* ORACLE_PERIODIC or ORACLE_DIRICHLET */
+    int32_t bc;          /* ORACLE_PERIODIC, ORACLE_DIRICHLET, or ORACLE_REFLECTIVE (heat only:
+                            the insulated ends of Appendix B, Eq. heatcond) */
     int64_t n;           /* grid points (heat, KS) or cells (Euler) */
     int64_t nsteps;      /* full timesteps */
     double dt, dx;

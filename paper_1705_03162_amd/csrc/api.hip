@@ -155,7 +155,7 @@ int run_swept(sw_plan *p, double *state, hipStream_t st)
 int enqueue_classic(sw_plan *p, double *state, int64_t steps, int64_t step0, hipStream_t st)
 {
     const Geom &g = p->geom;
-    const int dir = g.bc == SW_DIRICHLET ? 1 : 0;
+    const int dir = g.bc;  // BcKind
     for (int64_t m = 0; m < steps; ++m) {
         hipError_t e;
         if (g.S == 1) {

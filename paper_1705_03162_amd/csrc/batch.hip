@@ -166,7 +166,7 @@ SolveDesc make_desc(const Ticket &t)
     d.w = t.geom.w;
     d.H = t.geom.H;
     d.E = t.geom.E;
-    d.dirichlet = t.geom.bc == SW_DIRICHLET ? 1 : 0;
+    d.bc = t.geom.bc;
     d.nphases = phase_count(t.geom.Q, t.geom.rem);
     d.phase = t.phase;
     d.c = make_consts(t.prob);

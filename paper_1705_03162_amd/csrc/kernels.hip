@@ -99,19 +99,30 @@ __device__ __forceinline__ void level_step(const TileArgs &a, int g, int NW, int
     const int x0 = g * P;  // first tile position of this lane
     // The tile's outer halo is read by the widest level of a Diamond/Down only.
     if (s == a.H && a.kind != PH_UP) {
+        const bool refl = a.bc == BC_REFLECTIVE;  // heat only: R == 1
         if (x0 < R) {
+            if (refl && (a.ends & 1)) {
+                if constexpr (R == 1)
+                    if (x0 == 0) ext[0][0] = ext[0][mirror_left_src(R, 0)];
+            } else {
 #pragma unroll
-            for (int v = 0; v < NV; ++v)
+                for (int v = 0; v < NV; ++v)
 #pragma unroll
-                for (int i = 0; i < R; ++i)
-                    if (x0 - R + i < 0) ext[v][i] = hl[v][x0 + i];
+                    for (int i = 0; i < R; ++i)
+                        if (x0 - R + i < 0) ext[v][i] = hl[v][x0 + i];
+            }
         }
         if (x0 + P + R > a.w) {
+            if (refl && (a.ends & 2)) {
+                if constexpr (R == 1)
+                    if (x0 + P == a.w) ext[0][R + P] = ext[0][mirror_right_src(P, R, 0)];
+            } else {
 #pragma unroll
-            for (int v = 0; v < NV; ++v)
+                for (int v = 0; v < NV; ++v)
 #pragma unroll
-                for (int i = 0; i < R; ++i)
-                    if (x0 + P + i >= a.w) ext[v][R + P + i] = hr[v][x0 + P + i - a.w];
+                    for (int i = 0; i < R; ++i)
+                        if (x0 + P + i >= a.w) ext[v][R + P + i] = hr[v][x0 + P + i - a.w];
+            }
         }
     }
     if (MULTI) {
@@ -131,7 +142,12 @@ __device__ __forceinline__ void level_step(const TileArgs &a, int g, int NW, int
                         ext[v][R + P + i] = xch[buf][wave + 1][0][v][lane * P + P + i - 64 * P];
         }
     }
-    if (WALL) {  // Dirichlet wall at the tile centre: across it lie the ghost values
+    if (WALL && a.bc == BC_REFLECTIVE) {  // insulated ends meet at the tile centre (heat, R == 1)
+        if constexpr (R == 1) {
+            if (x0 == half) ext[0][0] = ext[0][mirror_left_src(R, 0)];
+            if (x0 + P == half) ext[0][R + P] = ext[0][mirror_right_src(P, R, 0)];
+        }
+    } else if (WALL) {  // Dirichlet wall at the tile centre: across it lie the ghost values
         if (x0 >= half && x0 - R < half) {
 #pragma unroll
             for (int v = 0; v < NV; ++v)
@@ -217,10 +233,12 @@ __device__ __forceinline__ void run_levels(const TileArgs &a, int g, int NW, dou
 
 // One tile of one phase: load the two rows, run the phase's levels, store.
 template <class Sch, int P>
-__device__ __forceinline__ void tile_body(const TileArgs &a, int64_t j, int g, int NW,
+__device__ __forceinline__ void tile_body(const TileArgs &args, int64_t j, int g, int NW,
                                           double (*xch)[16][2][Sch::NV][Sch::R])
 {
     constexpr int NV = Sch::NV, R = Sch::R;
+    TileArgs a = args;
+    a.ends = tile_ends(args, j);
     double r0[NV][P], r1[NV][P], hl[NV][R], hr[NV][R];
     lane_load<Sch, P>(a, j, g, r0, r1, hl, hr);
     const bool wall = straddles_wall(a, j);
@@ -265,8 +283,8 @@ __global__ __launch_bounds__(64) void batch_tiles(const SolveDesc *__restrict__ 
         a.w = d.w;
         a.H = d.H;
         a.E = d.E;
-        a.dirichlet = d.dirichlet;
-        a.pad = 0;
+        a.bc = d.bc;
+        a.ends = 0;
         a.c = d.c;
         phase_at(d.Q, d.rem, d.H, p, a.kind, a.levels, a.offset);
         tile_body<Sch, P>(a, (int64_t)it.y, (int)threadIdx.x, 1, xch);
@@ -277,7 +295,7 @@ __global__ __launch_bounds__(64) void batch_tiles(const SolveDesc *__restrict__ 
 // final RK2 stage `dst` holds u^m and is updated in place (the listing's +=).
 template <class Sch>
 __global__ __launch_bounds__(256) void classic_level(const double *__restrict__ src, double *dst,
-                                                     int64_t n, int dirichlet, int predictor, Consts c)
+                                                     int64_t n, int bc, int predictor, Consts c)
 {
     constexpr int NV = Sch::NV, R = Sch::R;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -288,7 +306,9 @@ __global__ __launch_bounds__(256) void classic_level(const double *__restrict__ 
     for (int d = 0; d < 2 * R + 1; ++d) {
         int64_t jj = i - R + d;
         const bool inside = jj >= 0 && jj < n;
+        const bool dirichlet = bc == BC_DIRICHLET;
         if (dirichlet) jj = jj < 0 ? 0 : (jj >= n ? n - 1 : jj);
+        else if (bc == BC_REFLECTIVE) jj = jj < 0 ? -jj : (jj >= n ? 2 * (n - 1) - jj : jj);  // R == 1, n >= 2
         else if (tiny) jj = ((jj % n) + n) % n;
         else jj = jj < 0 ? jj + n : (jj >= n ? jj - n : jj);
 #pragma unroll
@@ -353,17 +373,17 @@ hipError_t launch_swept_phase(int scheme, int P, int threads, const TileArgs &a,
     return launch_tile_p<Euler>(a, P, threads, st);
 }
 
-hipError_t launch_classic_level(int scheme, const double *src, double *dst, int64_t n, int dirichlet,
+hipError_t launch_classic_level(int scheme, const double *src, double *dst, int64_t n, int bc,
                                 int predictor, const Consts &c, hipStream_t st)
 {
     const int T = 256;
     const unsigned blocks = (unsigned)((n + T - 1) / T);
     if (scheme == 0)
-        hipLaunchKernelGGL(classic_level<Heat>, dim3(blocks), dim3(T), 0, st, src, dst, n, dirichlet, predictor, c);
+        hipLaunchKernelGGL(classic_level<Heat>, dim3(blocks), dim3(T), 0, st, src, dst, n, bc, predictor, c);
     else if (scheme == 1)
-        hipLaunchKernelGGL(classic_level<KS>, dim3(blocks), dim3(T), 0, st, src, dst, n, dirichlet, predictor, c);
+        hipLaunchKernelGGL(classic_level<KS>, dim3(blocks), dim3(T), 0, st, src, dst, n, bc, predictor, c);
     else
-        hipLaunchKernelGGL(classic_level<Euler>, dim3(blocks), dim3(T), 0, st, src, dst, n, dirichlet, predictor, c);
+        hipLaunchKernelGGL(classic_level<Euler>, dim3(blocks), dim3(T), 0, st, src, dst, n, bc, predictor, c);
     return hipGetLastError();
 }
 

@@ -11,7 +11,7 @@ namespace sw {
 hipError_t launch_swept_phase(int scheme, int P, int threads, const TileArgs &a, hipStream_t st);
 
 // One classic sub-step over n points: src -> dst (in place on dst for a final RK2 stage).
-hipError_t launch_classic_level(int scheme, const double *src, double *dst, int64_t n, int dirichlet,
+hipError_t launch_classic_level(int scheme, const double *src, double *dst, int64_t n, int bc,
                                 int predictor, const Consts &c, hipStream_t st);
 
 // One phase of many independent solves: items[i] = (solve index into desc, tile).

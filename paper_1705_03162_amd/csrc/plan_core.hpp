@@ -51,7 +51,13 @@ inline int validate_problem(const sw_problem *p, std::string *err)
 {
     if (!p) { *err = "problem is NULL"; return SW_EINVAL; }
     if (p->scheme < SW_HEAT || p->scheme > SW_EULER) { *err = "unknown scheme"; return SW_EINVAL; }
-    if (p->bc != SW_PERIODIC && p->bc != SW_DIRICHLET) { *err = "unknown boundary type"; return SW_EINVAL; }
+    if (p->bc != SW_PERIODIC && p->bc != SW_DIRICHLET && p->bc != SW_REFLECTIVE) {
+        *err = "unknown boundary type"; return SW_EINVAL;
+    }
+    if (p->bc == SW_REFLECTIVE && (p->scheme != SW_HEAT || p->n < 2)) {
+        *err = "reflective ends are defined for the heat equation (Appendix B) with n >= 2";
+        return SW_EINVAL;
+    }
     if (p->n < 1) { *err = "n must be >= 1"; return SW_EINVAL; }
     if (p->nsteps < 0) { *err = "nsteps must be >= 0"; return SW_EINVAL; }
     if (!(p->dt > 0.0) || !std::isfinite(p->dt)) { *err = "dt must be finite and > 0"; return SW_EINVAL; }
@@ -147,7 +153,8 @@ inline TileArgs make_tile_args(const Geom &g, const Consts &c, const Phase &ph, 
     a.state = state; a.edges = edges;
     a.n = g.n; a.K = g.K; a.w = g.w; a.H = g.H; a.E = g.E;
     a.kind = ph.kind; a.levels = ph.levels; a.offset = ph.offset;
-    a.dirichlet = g.bc == SW_DIRICHLET ? 1 : 0;
+    a.bc = g.bc;
+    a.ends = 0;
     a.c = c;
     return a;
 }

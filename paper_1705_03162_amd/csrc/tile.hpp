@@ -33,6 +33,8 @@
 namespace sw {
 
 enum PhaseKind : int32_t { PH_UP = 0, PH_DIAMOND = 1, PH_DOWN = 2 };
+// Boundary types (the values of SW_PERIODIC, SW_DIRICHLET, SW_REFLECTIVE).
+enum BcKind : int32_t { BC_PERIODIC = 0, BC_DIRICHLET = 1, BC_REFLECTIVE = 2 };
 
 // Largest work-group for which a tile kernel is compiled: the two rows take
 // 2*nv*P doubles per lane, and the register file must hold them for every wave.
@@ -49,8 +51,9 @@ struct TileArgs {
     int32_t kind;      // PhaseKind
     int32_t levels;    // Up/Down: levels to advance (<= H); Diamond: ignored (2H - 1)
     int32_t offset;    // 0, or 1 for tiles shifted by w/2
-    int32_t dirichlet; // 1: the tile straddling the domain end sees ghost values
-    int32_t pad;
+    int32_t bc;        // BC_PERIODIC, BC_DIRICHLET or BC_REFLECTIVE
+    int32_t ends;      // set per tile: bit 0 = its left edge is the domain's left end,
+                       // bit 1 = its right edge is the right end (non-periodic only)
     Consts c;
 };
 
@@ -59,7 +62,7 @@ struct SolveDesc {
     double *state;
     double *edges;
     int64_t n, K, Q, rem;
-    int32_t w, H, E, dirichlet;
+    int32_t w, H, E, bc;
     int32_t nphases;   // phase_count(Q, rem)
     int32_t phase;     // next phase to run (served batches advance solves independently)
     Consts c;
@@ -121,8 +124,25 @@ SW_HD int half_width(const TileArgs &a, int s)
 // half = the first w/2 points, each seeing ghost values across the wall.
 SW_HD bool straddles_wall(const TileArgs &a, int64_t j)
 {
-    return a.dirichlet && a.offset == 1 && j == a.K - 1;
+    return a.bc != BC_PERIODIC && a.offset == 1 && j == a.K - 1;
 }
+
+// In unshifted phases of a non-periodic problem, the first tile's left edge and
+// the last tile's right edge are the ends of the domain.
+SW_HD int32_t tile_ends(const TileArgs &a, int64_t j)
+{
+    if (a.bc == BC_PERIODIC || a.offset != 0) return 0;
+    return (j == 0 ? 1 : 0) | (j == a.K - 1 ? 2 : 0);
+}
+
+// Reflective (insulated) ends, heat only (r = 1): the ghost beyond an end mirrors
+// the point one inside it (T_{-1} = T_1, T_N = T_{N-2}).  For a lane whose first
+// point is the domain's first point, its left halo entry i mirrors ext index
+// 2R - i; for a lane whose last point is the domain's last, its right halo entry
+// i mirrors ext index P + R - 2 - i (ext covers the lane's points and R halo
+// points per side).
+SW_HD constexpr int mirror_left_src(int R, int i) { return 2 * R - i; }
+SW_HD constexpr int mirror_right_src(int P, int R, int i) { return P + R - 2 - i; }
 
 // Load lane g's rows.  Up: row 0 = the current full level from the state.
 // Diamond/Down: both rows from the two source slots, plus the r points just
@@ -170,7 +190,7 @@ SW_HD void lane_load(const TileArgs &a, int64_t j, int g, double (&r0)[Sch::NV][
     }
     // Dirichlet: in unshifted phases the first tile starts at the left wall and
     // the last ends at the right wall, so the points beyond them are ghosts.
-    if (a.dirichlet && a.offset == 0) {
+    if (a.bc == BC_DIRICHLET && a.offset == 0) {
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
 #pragma unroll

@@ -68,7 +68,7 @@ def time_shape(sw, torch, prob, ic, width, threads, reps):
 
 
 def tune(schemes=(0, 1, 2), log2ns=range(12, 21), target_s: float = 0.02, reps: int = 3,
-         table: str = TABLE, log=print):
+         table: str = TABLE, log=print, verbose: bool = False):
     import torch
 
     import paper_1705_03162_amd as sw
@@ -89,6 +89,10 @@ def tune(schemes=(0, 1, 2), log2ns=range(12, 21), target_s: float = 0.02, reps: 
             for w, th in shapes:
                 t = time_shape(sw, torch, prob, ic, w, th, reps)
                 results.append((t, w, th))
+            if verbose:
+                for tt, ww, tth in results:
+                    log(f"  shape w={ww} T={tth} P={ww // tth} waves={tth // 64}: "
+                        f"{n * steps / tt:.3e} pt-upd/s")
             results.sort()
             t, w, th = results[0]
             rate = n * steps / t
@@ -109,13 +113,14 @@ def main():
     ap.add_argument("--log2n", default="12-20")
     ap.add_argument("--table", default=TABLE)
     ap.add_argument("--target-ms", type=float, default=20.0)
+    ap.add_argument("--verbose", action="store_true", help="log every shape timed")
     args = ap.parse_args()
     names = {"heat": 0, "ks": 1, "euler": 2}
     schemes = [names[s] for s in args.schemes.split(",")]
     a, b = (int(x) for x in args.log2n.split("-"))
     sys.path.insert(0, os.path.dirname(HERE))
     tune(schemes, range(a, b + 1), target_s=args.target_ms / 1000.0, table=args.table,
-         log=lambda m: print(m, flush=True))
+         log=lambda m: print(m, flush=True), verbose=args.verbose)
 
 
 if __name__ == "__main__":

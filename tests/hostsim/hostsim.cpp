@@ -49,10 +49,23 @@ void run_phase(const Geom &g, const TileArgs &a)
                                             : (outer ? L[0].hl[v][ql + R] : 0.0);
                         ext[v][R + P + i] = qr < a.w ? (odd ? L[qr / P].r0 : L[qr / P].r1)[v][qr % P]
                                                      : (outer ? L[0].hr[v][qr - a.w] : 0.0);
-                        // Dirichlet wall at the tile centre: across it lie the ghosts
-                        if (wall && l * P >= a.w / 2 && ql < a.w / 2) ext[v][i] = a.c.ghost_l[v];
-                        if (wall && l * P < a.w / 2 && qr >= a.w / 2) ext[v][R + P + i] = a.c.ghost_r[v];
+                        if (a.bc == BC_DIRICHLET) {
+                            // Dirichlet wall at the tile centre: across it lie the ghosts
+                            if (wall && l * P >= a.w / 2 && ql < a.w / 2) ext[v][i] = a.c.ghost_l[v];
+                            if (wall && l * P < a.w / 2 && qr >= a.w / 2) ext[v][R + P + i] = a.c.ghost_r[v];
+                        }
                     }
+                }
+                if (a.bc == BC_REFLECTIVE) {
+                    // insulated ends: the point beyond an end takes the value one point
+                    // inside it (domain point -1 <- 1, n <- n-2), by tile position
+                    auto at = [&](int q) { return (odd ? L[q / P].r0 : L[q / P].r1)[0][q % P]; };
+                    const int ends = tile_ends(a, j), half = a.w / 2;
+                    const int ql = l * P - 1, qr = l * P + P;
+                    if (outer && (ends & 1) && ql == -1) ext[0][0] = at(1);
+                    if (outer && (ends & 2) && qr == a.w) ext[0][P + 1] = at(a.w - 2);
+                    if (wall && l * P == half) ext[0][0] = at(half + 1);
+                    if (wall && qr == half) ext[0][P + 1] = at(half - 2);
                 }
                 // element masks exactly as the kernel derives them (residues from s mod G)
                 const int m = half_width(a, s);

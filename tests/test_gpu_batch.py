@@ -48,6 +48,9 @@ def test_ensemble_each_result_equals_alone(oracle_mod):
     probs = mixed_problems(48, seed=1)
     probs.append((W.heat_problem(1000, 77), W.fourier_ic(1000, 5)))   # no swept width: classic
     probs.append((W.ks_problem(4096, 0), W.fourier_ic(4096, 6)))      # zero steps
+    probs.append((W.heat_problem(2048, 613, bc=W.REFLECTIVE), W.fourier_ic(2048, 7)))
+    probs.append((W.heat_problem(1024, 420, bc=W.DIRICHLET, bc_left=0.5, bc_right=-0.5),
+                  W.fourier_ic(1024, 8)))
     print(f"[gpu] ensemble of {len(probs)} solves", flush=True)
     states = [torch.tensor(ic, dtype=torch.float64, device=DEV) for _, ic in probs]
     with sw.Batch(budget_bytes=1 << 34) as b:
@@ -57,7 +60,7 @@ def test_ensemble_each_result_equals_alone(oracle_mod):
             assert b.poll(t) == N.SW_TICKET_DONE
         infos = [b.info(t) for t in tickets]
     torch.cuda.synchronize()
-    assert infos[-2]["swept"] == 0
+    assert infos[-4]["swept"] == 0
     for (prob, ic), x in zip(probs, states):
         assert np.array_equal(x.cpu().numpy(), alone(prob, ic))
     for prob, ic in probs[:6]:

@@ -62,6 +62,11 @@ SMALL = [  # (problem factory, width, threads)
     (lambda: (W.ks_problem(1024, 257), W.fourier_ic(1024, 12)), 256, 256),
     (lambda: (W.sod_problem(448, 350), W.sod_ic(448)), 64, 64),
     (lambda: (W.sod_problem(1024, 200), W.sod_ic(1024)), 128, 128),
+    # insulated (reflective) heat ends: wall tile at the centre of shifted phases
+    (lambda: (W.heat_problem(1024, 501, bc=W.REFLECTIVE), W.fourier_ic(1024, 13)), 64, 64),
+    (lambda: (W.heat_problem(4096, 1999, bc=W.REFLECTIVE), W.fourier_ic(4096, 14)), 1024, 256),
+    (lambda: (W.heat_problem(2048, 700, bc=W.REFLECTIVE), W.fourier_ic(2048, 15)), 2048, 128),
+    (lambda: (W.heat_problem(512, 333, bc=W.REFLECTIVE), W.fourier_ic(512, 16)), 128, 128),
 ]
 
 
@@ -237,6 +242,13 @@ def test_tiny_and_ragged_grids_classic(oracle_mod, n, scheme):
     assert np.array_equal(got, oracle_mod.solve(prob, ic))
 
 
+@pytest.mark.parametrize("n", [2, 3, 5, 100])
+def test_tiny_reflective_heat_classic(oracle_mod, n):
+    prob = W.heat_problem(n, 41, bc=W.REFLECTIVE)
+    ic = W.random_ic(n, 1, seed=100 + n)
+    assert np.array_equal(gpu_solve(prob, ic, "classic"), oracle_mod.solve(prob, ic))
+
+
 def test_ragged_grid_euler_dirichlet_classic(oracle_mod):
     prob = W.sod_problem(1000, 300)
     ic = W.sod_ic(1000)
@@ -277,5 +289,6 @@ def test_nan_check_flag():
 def test_large_dirichlet_heat_and_sod_swept_equals_classic():
     for prob, ic in ((W.heat_problem(1 << 18, 5000, bc=W.DIRICHLET, bc_left=1.0, bc_right=-1.0),
                       W.fourier_ic(1 << 18, 3)),
+                     (W.heat_problem(1 << 18, 5000, bc=W.REFLECTIVE), W.fourier_ic(1 << 18, 4)),
                      (W.sod_problem(1 << 16, 3000), W.sod_ic(1 << 16))):
         assert np.array_equal(gpu_solve(prob, ic, "swept"), gpu_solve(prob, ic, "classic"))

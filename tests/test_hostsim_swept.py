@@ -74,7 +74,7 @@ HEAT_CASES = [  # (n, steps, width, threads)
 
 
 @pytest.mark.parametrize("n,steps,width,threads", HEAT_CASES)
-@pytest.mark.parametrize("bc", [W.PERIODIC, W.DIRICHLET])
+@pytest.mark.parametrize("bc", [W.PERIODIC, W.DIRICHLET, W.REFLECTIVE])
 def test_heat_swept_equals_oracle(hostsim, oracle_mod, n, steps, width, threads, bc):
     prob = W.heat_problem(n, steps, bc=bc, bc_left=0.3, bc_right=-0.7)
     ic = W.fourier_ic(n, seed=n + steps) + 0.1 * W.random_ic(n, 1, seed=steps)

@@ -62,6 +62,36 @@ def test_heat_dirichlet_zero_closed_form(oracle_mod, fo):
     assert np.abs(got - want).max() <= (8 + 1.5 * m) * EPS * np.abs(ic).max() * 4
 
 
+@pytest.mark.parametrize("fo", [0.25, 0.4])
+def test_heat_reflective_closed_form(oracle_mod, fo):
+    """Insulated ends (Eq. heatcond, mirror ghosts T_{-1} = T_1, T_N = T_{N-2}): modes
+    cos(pi k i/(N-1)) are eigenvectors with factor 1 - 4 Fo sin^2(pi k/(2(N-1)))."""
+    n, m = 80, 400
+    mpmath.mp.dps = 40
+    ks, amps = [0, 1, 4, 9], [0.3, 0.7, -0.4, 0.25]
+    ic = np.zeros(n)
+    want = np.zeros(n)
+    for k, a in zip(ks, amps):
+        g = 1 - 4 * mpmath.mpf(fo) * mpmath.sin(mpmath.pi * k / (2 * (n - 1))) ** 2
+        for i in range(n):
+            c = mpmath.cos(mpmath.pi * k * i / (n - 1))
+            ic[i] += float(a * c)
+            want[i] += float(a * c * g ** m)
+    prob = W.heat_problem(n, m, bc=W.REFLECTIVE, fo=fo)
+    got = oracle_mod.solve(prob, ic.reshape(1, n))[0]
+    assert np.abs(got - want).max() <= (8 + 1.5 * m) * EPS * np.abs(ic).max() * 4
+
+
+def test_heat_reflective_conserves_trapezoid_sum(oracle_mod):
+    """With mirror ghosts the trapezoid-weighted sum (end points weighted 1/2) is
+    conserved: the flux through each insulated end vanishes."""
+    n = 123
+    ic = W.random_ic(n, 1, seed=31)[0]
+    got = oracle_mod.solve(W.heat_problem(n, 300, bc=W.REFLECTIVE), ic.reshape(1, n))[0]
+    trap = lambda u: u[1:-1].sum() + 0.5 * (u[0] + u[-1])
+    assert abs(trap(got) - trap(ic)) < 1e-12 * n
+
+
 def test_heat_max_principle_and_conservation(oracle_mod):
     n = 777
     ic = W.random_ic(n, 1, seed=11)

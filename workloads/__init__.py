@@ -21,7 +21,7 @@ import numpy as np
 
 # Scheme and boundary identifiers (same numeric values as the C interfaces).
 HEAT, KS, EULER = 0, 1, 2
-PERIODIC, DIRICHLET = 0, 1
+PERIODIC, DIRICHLET, REFLECTIVE = 0, 1, 2
 SCHEME_NAMES = {HEAT: "heat", KS: "ks", EULER: "euler"}
 NVARS = {HEAT: 1, KS: 1, EULER: 3}
 
