@@ -15,7 +15,9 @@ the host's cores on a bounded sample.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -35,6 +37,42 @@ PEAK_HBM_GBS = 8000.0
 # Algorithmic FP64 operations per point per sub-step level (add/sub/mul/neg-free),
 # as written in the canonical update rules.
 FLOPS_PER_POINT_LEVEL = {W.HEAT: 4, W.KS: 18}
+# Algorithmic HBM bytes per point-update of the classic decomposition (state read
+# and written once per sub-step: heat 8r+8w; KS predictor 8r+8w, final 16r+8w;
+# Euler 3 variables over two sub-steps).
+CLASSIC_BYTES_PER_UPDATE = {W.HEAT: 16, W.KS: 40, W.EULER: 120}
+
+# Sources that determine the swept tile kernel's machine code, and the committed
+# hardware-counter summary of its KS Diamond launch at N = 2^20.
+KERNEL_SOURCES = ("paper_1705_03162_amd/csrc/kernels.hip", "paper_1705_03162_amd/csrc/tile.hpp",
+                  "paper_1705_03162_amd/csrc/schemes.hpp", "paper_1705_03162_amd/build.py")
+TRAFFIC_SUMMARY = "profiles/swept_tile_ks_diamond_n2p20_pmc.txt"
+
+
+def kernel_digest() -> str:
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(width: int, threads: int):
+    """HBM bytes per launch of the KS Diamond from the committed counter summary
+    (lines '@key value'), or None when the kernel sources or the tile shape differ
+    from those the counters were taken on."""
+    try:
+        with open(os.path.join(ROOT, TRAFFIC_SUMMARY)) as f:
+            kv = dict(line[1:].split(None, 1) for line in f.read().splitlines()
+                      if line.startswith("@") and len(line.split()) >= 2)
+    except OSError:
+        return None
+    kv = {k: v.strip() for k, v in kv.items()}
+    if kv.get("kernel_digest") != kernel_digest():
+        return None
+    if int(kv.get("width", -1)) != width or int(kv.get("threads", -1)) != threads:
+        return None
+    return float(kv["hbm_bytes_per_launch"])
 
 
 def log(msg):
@@ -73,20 +111,22 @@ def cpu_baseline(budget_s: float = 12.0):
             "kind": "oracle", "sample": "; ".join(samples) + f" of the {NSTEPS}-step workload"}
 
 
-def rate_of(sw, torch, prob, ic, kind, flags=0, reps=2):
-    """Best-of-reps point-updates/s of one solve (state resident, graph captured)."""
-    with sw.Plan(prob, flags=flags) as plan:
+def rate_of(sw, torch, prob, ic, kind, flags=0, reps=2, width=0, threads=0, stat=min):
+    """Point-updates/s of one solve (state resident, graph captured), from the best
+    (or, with stat=np.median, the median) of `reps` timed runs after one warm run."""
+    with sw.Plan(prob, width, threads, flags) as plan:
         x0 = torch.tensor(ic, dtype=torch.float64, device="cuda")
         x = x0.clone()
         getattr(plan, kind)(x)
-        best = float("inf")
+        times = []
         for _ in range(reps):
             x.copy_(x0)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             getattr(plan, kind)(x)
             torch.cuda.synchronize()
-            best = min(best, time.perf_counter() - t0)
+            times.append(time.perf_counter() - t0)
+        best = float(stat(times))
         info = plan.info()
     return prob.n * prob.nsteps / best, best, info, x
 
@@ -192,8 +232,46 @@ def serve_run(rate=2000.0, duration_s=0.25, seed=5, max_slots=0, fifo=True):
     return out
 
 
+def legal_p(scheme):
+    return (1, 2, 4, 8) if scheme == W.EULER else (1, 2, 4, 8, 16)
+
+
+def search_shapes(sw, torch, prob, ic, shapes):
+    """Best (rate, width, threads) of the swept solve over the given tile shapes."""
+    best = None
+    for w, t in shapes:
+        if prob.n % w:
+            continue
+        try:
+            r, _, _, _ = rate_of(sw, torch, prob, ic, "swept", reps=1, width=w, threads=t)
+        except sw.SweptError:
+            continue
+        if best is None or r > best[0]:
+            best = (r, w, t)
+    return best
+
+
+def e2e_seconds(sw, torch, prob, ic, kind):
+    """Paper-style end-to-end time: plan and device allocation, host-to-device copy of
+    the initial state, the solve, device-to-host copy of the result."""
+    host = np.ascontiguousarray(ic)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    with sw.Plan(prob) as plan:
+        x = torch.from_numpy(host).to("cuda")
+        getattr(plan, kind)(x)
+        out = x.cpu()
+    dt = time.perf_counter() - t0
+    del out
+    return dt
+
+
 def suite_sweep(schemes, log2ns, max_steps):
-    """One JSON line per (scheme, N): swept vs classic (graph and stream launches)."""
+    """One JSON line per (scheme, N): the tuned swept solve (median of 5), the best
+    one-wave "register" tile, the best one-point-per-thread tile (w = T, the paper's
+    layout), classic through replayed graphs and through stream launches, the
+    end-to-end times of both, and the swept rate against the classic HBM roofline and
+    the FP64 VALU ceiling."""
     import torch
     import paper_1705_03162_amd as sw
     for scheme in schemes:
@@ -204,16 +282,215 @@ def suite_sweep(schemes, log2ns, max_steps):
                 prob, ic = W.cfg_sweep(scheme, lg)
             full = prob.nsteps
             prob = prob.with_steps(min(full, max_steps))
-            rs, ts, info, xs = rate_of(sw, torch, prob, ic, "swept")
-            rg, tg, _, xg = rate_of(sw, torch, prob, ic, "classic")
+            rs, ts, info, xs = rate_of(sw, torch, prob, ic, "swept", reps=5, stat=np.median)
+            rg, tg, _, xg = rate_of(sw, torch, prob, ic, "classic", reps=3, stat=np.median)
             rst, tst, _, _ = rate_of(sw, torch, prob, ic, "classic", flags=sw.SW_TUNE_NO_GRAPH, reps=1)
             same = bool(torch.equal(xs, xg))
-            print(json.dumps({"scheme": W.SCHEME_NAMES[scheme], "n": prob.n, "steps": prob.nsteps,
-                              "full_steps": full, "swept": rs, "classic_graph": rg,
-                              "classic_stream": rst, "swept_over_classic_graph": rs / rg,
-                              "swept_over_classic_stream": rs / rst, "swept_ms": ts * 1e3,
-                              "classic_graph_ms": tg * 1e3, "width": info["width"],
-                              "threads": info["threads"], "bitwise_equal": same}), flush=True)
+            reg = search_shapes(sw, torch, prob, ic, [(64 * p, 64) for p in legal_p(scheme)])
+            p1 = search_shapes(sw, torch, prob, ic, [(t, t) for t in (64, 128, 256, 512, 1024)])
+            e2e_s = e2e_seconds(sw, torch, prob, ic, "swept")
+            e2e_c = e2e_seconds(sw, torch, prob, ic, "classic")
+            upd = prob.n * prob.nsteps
+            roof = PEAK_HBM_GBS * 1e9 / CLASSIC_BYTES_PER_UPDATE[scheme]
+            line = {"scheme": W.SCHEME_NAMES[scheme], "n": prob.n, "steps": prob.nsteps,
+                    "full_steps": full, "swept": rs, "classic_graph": rg, "classic_stream": rst,
+                    "swept_over_classic_graph": rs / rg, "swept_over_classic_stream": rs / rst,
+                    "swept_ms": ts * 1e3, "classic_graph_ms": tg * 1e3,
+                    "width": info["width"], "threads": info["threads"], "bitwise_equal": same,
+                    "register_best": None if reg is None else {"rate": reg[0], "width": reg[1], "threads": reg[2]},
+                    "one_point_per_thread_best": None if p1 is None else {"rate": p1[0], "width": p1[1], "threads": p1[2]},
+                    "e2e_swept": upd / e2e_s, "e2e_classic": upd / e2e_c,
+                    "classic_hbm_roofline": roof, "swept_over_classic_roofline": rs / roof}
+            if scheme in FLOPS_PER_POINT_LEVEL:
+                ops = rs * FLOPS_PER_POINT_LEVEL[scheme] * (2 if scheme == W.KS else 1)
+                line["swept_fp64_tflops"] = ops / 1e12
+                line["swept_frac_fp64_peak"] = ops / (PEAK_FP64_TFLOPS * 1e12)
+            print(json.dumps(line), flush=True)
+            log(f"{W.SCHEME_NAMES[scheme]} 2^{lg}: swept {rs:.3e} classic graph {rg:.3e} "
+                f"stream {rst:.3e} e2e swept {upd / e2e_s:.3e}")
+
+
+def device_fourier_ic(torch, n, seed, kmax=16):
+    """Smooth periodic field built on the device (same modes as the host generator,
+    for sizes where evaluating it on the host would dominate the run)."""
+    rng = np.random.default_rng(seed)
+    kmax = max(1, min(kmax, n // 8)) if n >= 8 else 1
+    a = rng.uniform(-1.0, 1.0, kmax)
+    b = rng.uniform(-1.0, 1.0, kmax)
+    i = torch.arange(n, dtype=torch.float64, device="cuda")
+    x = torch.zeros(n, dtype=torch.float64, device="cuda")
+    for k in range(kmax):
+        th = i * (2.0 * math.pi * (k + 1) / n)
+        x += float(a[k]) * torch.cos(th) + float(b[k]) * torch.sin(th)
+    return x.reshape(1, n)
+
+
+def device_ic(torch, prob, seed):
+    if prob.scheme == W.EULER:
+        return torch.tensor(W.sod_ic(prob.n), dtype=torch.float64, device="cuda")
+    return device_fourier_ic(torch, prob.n, seed)
+
+
+def copy_bandwidth(torch, nbytes=1 << 30, reps=10):
+    """Achievable HBM bandwidth: a plain device copy of `nbytes` (read + write)."""
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    return 2 * nbytes / dt / 1e9
+
+
+def suite_anchors(steps=200):
+    """Out-of-cache anchors: classic and swept at sizes whose state exceeds the
+    on-chip caches (heat, KS at 2^26; Euler at 2^24), against a plain copy."""
+    import torch
+    import paper_1705_03162_amd as sw
+    bw = copy_bandwidth(torch)
+    print(json.dumps({"anchor": "copy", "bytes": 1 << 30, "gb_per_s": bw,
+                      "frac_of_peak": bw / PEAK_HBM_GBS}), flush=True)
+    for scheme, lg in ((W.HEAT, 26), (W.KS, 26), (W.EULER, 24)):
+        n = 1 << lg
+        prob = {W.HEAT: W.heat_problem, W.KS: W.ks_problem}[scheme](n, steps) if scheme != W.EULER \
+            else W.sod_problem(n, steps // 2)
+        x0 = device_ic(torch, prob, seed=lg)
+        out = {"anchor": W.SCHEME_NAMES[scheme], "n": n, "steps": prob.nsteps}
+        for kind, flags in (("classic", 0), ("swept", 0)):
+            with sw.Plan(prob, flags=flags) as plan:
+                x = x0.clone()
+                getattr(plan, kind)(x)
+                x.copy_(x0)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                getattr(plan, kind)(x)
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+                out[kind] = n * prob.nsteps / dt
+                if kind == "swept":
+                    out["width"], out["threads"] = plan.info()["width"], plan.info()["threads"]
+        gbs = out["classic"] * CLASSIC_BYTES_PER_UPDATE[scheme] / 1e9
+        out.update({"classic_algorithmic_gb_per_s": gbs, "classic_frac_of_copy": gbs / bw,
+                    "classic_frac_of_peak_hbm": gbs / PEAK_HBM_GBS,
+                    "swept_over_classic": out["swept"] / out["classic"]})
+        print(json.dumps(out), flush=True)
+        log(f"anchor {W.SCHEME_NAMES[scheme]} 2^{lg}: classic {out['classic']:.3e} ({gbs:.0f} GB/s) "
+            f"swept {out['swept']:.3e}")
+        del x0
+
+
+def served(torch, sw, trace, warmup_s=0.0, max_slots=0):
+    """Feed a Poisson trace into a served batch in real time; latency = completion -
+    submission, over requests that arrived after the warm-up."""
+    states = [device_ic(torch, r.problem, r.ic_seed) for r in trace]
+    torch.cuda.synchronize()
+    upd = sum(r.problem.point_updates for r in trace)
+    with sw.Batch(budget_bytes=200 << 30, max_slots=max_slots, serve=True) as b:
+        t0 = time.perf_counter()
+        tickets = []
+        for r, x in zip(trace, states):
+            delay = r.arrival_s - (time.perf_counter() - t0)
+            if delay > 0:
+                time.sleep(delay)
+            tickets.append(b.submit(r.problem, x))
+        for t in tickets:
+            b.wait(t)
+        wall = time.perf_counter() - t0
+        infos = [b.info(t) for t in tickets]
+    keep = [(r, i) for r, i in zip(trace, infos) if r.arrival_s >= warmup_s]
+    lat = [i["end_s"] - i["submit_s"] for _, i in keep]
+    window = max(r.arrival_s for r in trace) - warmup_s if keep else 0.0
+    thirds = []
+    if keep:
+        span = max(r.arrival_s for r, _ in keep) - warmup_s
+        for q in range(3):
+            lo, hi = warmup_s + span * q / 3, warmup_s + span * (q + 1) / 3
+            sel = [i["end_s"] - i["submit_s"] for r, i in keep if lo <= r.arrival_s <= hi]
+            thirds.append(float(np.mean(sel)) if sel else None)
+    return {"requests": len(keep), "point_updates": upd, "wall_s": wall,
+            "throughput_point_updates_s": upd / wall, "p50_latency_s": pct(lat, 50),
+            "p99_latency_s": pct(lat, 99), "mean_latency_by_arrival_third_s": thirds,
+            "arrival_window_s": window}
+
+
+def suite_serve(rate=2000.0, duration_s=10.0, warmup_s=1.0, fifo_prefix=300):
+    """The configured serving run (Poisson arrivals at `rate` for `duration_s` after
+    `warmup_s`, then drain), the highest rate with a stable queue, and one solve at
+    a time, first come first served, on a prefix of the configured trace."""
+    import torch
+    import paper_1705_03162_amd as sw
+    trace = W.poisson_trace(rate=rate, duration_s=warmup_s + duration_s, seed=5)
+    log(f"serve: configured {rate}/s, {len(trace)} requests ...")
+    res = served(torch, sw, trace, warmup_s=warmup_s)
+    res.update({"run": "configured", "offered_rate_per_s": rate})
+    print(json.dumps(res), flush=True)
+
+    # sustainable rate: ascending offered rates on 3 s traces; stable when the mean
+    # latency of the last third of arrivals stays within 1.5x of the first third
+    stable = None
+    for r in (100.0, 200.0, 300.0, 400.0, 600.0, 800.0, 1200.0):
+        tr = W.poisson_trace(rate=r, duration_s=3.0, seed=6)
+        x = served(torch, sw, tr)
+        th = x["mean_latency_by_arrival_third_s"]
+        ok = th[0] is not None and th[2] is not None and th[2] <= 1.5 * th[0]
+        x.update({"run": "rate_search", "offered_rate_per_s": r, "stable": ok})
+        print(json.dumps(x), flush=True)
+        log(f"serve rate {r}/s: stable={ok} p50 {x['p50_latency_s']:.3f} s p99 {x['p99_latency_s']:.3f} s")
+        if not ok:
+            break
+        stable = x
+    print(json.dumps({"run": "sustainable", "rate_per_s": None if stable is None else stable["offered_rate_per_s"],
+                      "p50_latency_s": None if stable is None else stable["p50_latency_s"],
+                      "p99_latency_s": None if stable is None else stable["p99_latency_s"]}), flush=True)
+
+    # one solve at a time, FIFO, on the configured trace's first requests
+    pre = trace[:fifo_prefix]
+    lat = []
+    upd = sum(r.problem.point_updates for r in pre)
+    t0 = time.perf_counter()
+    for r in pre:
+        now = time.perf_counter() - t0
+        if now < r.arrival_s:
+            time.sleep(r.arrival_s - now)
+        x = device_ic(torch, r.problem, r.ic_seed)
+        with sw.Plan(r.problem, flags=sw.SW_TUNE_NO_GRAPH) as plan:
+            if plan.info()["swept_ok"]:
+                plan.swept(x)
+            else:
+                plan.classic(x)
+            torch.cuda.synchronize()
+        lat.append(time.perf_counter() - t0 - r.arrival_s)
+    wall = time.perf_counter() - t0
+    print(json.dumps({"run": "fifo_one_at_a_time", "requests": len(pre), "offered_rate_per_s": rate,
+                      "wall_s": wall, "throughput_point_updates_s": upd / wall,
+                      "p50_latency_s": pct(lat, 50), "p99_latency_s": pct(lat, 99)}), flush=True)
+
+
+def suite_oracle(budget_s=6.0):
+    """The CPU oracle on all host cores and on one core, bounded samples."""
+    import oracle
+    oracle.build(force=False)
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), None)
+    except OSError:
+        pass
+    affinity = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    for scheme, lg in ((W.HEAT, 20), (W.KS, 20), (W.EULER, 18)):
+        prob, ic = (W.cfg_sod(lg) if scheme == W.EULER else W.cfg_sweep(scheme, lg))
+        for nth in (0, 1):
+            probe = 4
+            _, s = oracle.solve(prob.with_steps(probe), ic, nthreads=nth, timed=True)
+            steps = max(probe, min(prob.nsteps, int(budget_s / max(s / probe, 1e-9))))
+            _, s = oracle.solve(prob.with_steps(steps), ic, nthreads=nth, timed=True)
+            print(json.dumps({"oracle": W.SCHEME_NAMES[scheme], "n": prob.n, "steps": steps,
+                              "threads": oracle.threads(nth), "affinity_cpus": affinity,
+                              "cpu_model": model, "seconds": s,
+                              "point_updates_s": prob.n * steps / s}), flush=True)
 
 
 def main():
@@ -224,13 +501,16 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-batch", action="store_true", help="skip the ensemble and serving runs")
     ap.add_argument("--profile-reps", type=int, default=30)
-    ap.add_argument("--suite", default="main", choices=["main", "sweep", "euler", "ensemble", "serve", "kernel"],
-                    help="main: the one-line benchmark; sweep/euler: per-N swept vs classic lines")
-    ap.add_argument("--max-steps", type=int, default=20_000)
+    ap.add_argument("--suite", default="main",
+                    choices=["main", "sweep", "euler", "ensemble", "serve", "kernel", "anchors", "oracle"],
+                    help="main: the one-line benchmark; sweep/euler: per-N swept vs classic lines; "
+                         "anchors: out-of-cache sizes and a copy; serve: configured and sustainable "
+                         "serving; oracle: CPU oracle on all cores and one; kernel: counter runs")
+    ap.add_argument("--max-steps", type=int, default=50_000)
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); every box here has one "
-              "GPU and nothing in this build uses a second.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the multi-GPU "
+              "decomposition is not implemented.", file=sys.stderr)
         sys.exit(2)
     if args.suite == "kernel":
         # for hardware-counter runs: a known-size device copy (calibrates FETCH/WRITE)
@@ -248,18 +528,26 @@ def main():
             info = plan.info()
         print(json.dumps({"copy_bytes": 2 * src.numel() * 8, "diamond_avg_us": us,
                           "width": info["width"], "threads": info["threads"],
-                          "levels_per_phase": info["levels_per_phase"], "n": prob.n}), flush=True)
+                          "levels_per_phase": info["levels_per_phase"], "n": prob.n,
+                          "kernel_digest": kernel_digest()}), flush=True)
+        return
+    if args.suite == "anchors":
+        suite_anchors()
+        return
+    if args.suite == "oracle":
+        suite_oracle()
         return
     if args.suite == "ensemble":
         print(json.dumps(ensemble_run()), flush=True)
         return
     if args.suite == "serve":
-        for rate, dur in ((2000.0, 1.0), (200.0, 5.0)):
-            print(json.dumps(serve_run(rate=rate, duration_s=dur)), flush=True)
+        suite_serve()
         return
     if args.suite != "main":
-        schemes = [W.EULER] if args.suite == "euler" else [W.HEAT, W.KS]
-        suite_sweep(schemes, range(12, 21), args.max_steps)
+        if args.suite == "euler":
+            suite_sweep([W.EULER], range(12, 21), args.max_steps)
+        else:
+            suite_sweep([W.HEAT, W.KS], range(12, 21, 2), args.max_steps)
         return
 
     import torch
@@ -336,15 +624,22 @@ def main():
         us = pl.profile_phase(scratch, kind=1, reps=args.profile_reps)
         launches = info["swept_launches"] - 3
         flops = n * info["levels_per_phase"] * FLOPS_PER_POINT_LEVEL[p.scheme]
+        # edge slots read and written by a Diamond: per tile 2 slots x nv x 2 rows x E doubles each way
+        edge_bytes = 2 * info["nodes"] * 2 * info["nvars"] * 2 * (info["width"] // 2 + info["radius"]) * 8
         kern.append({"scheme": W.SCHEME_NAMES[p.scheme], "avg_us": us, "flops_per_launch": flops,
-                     "launches_per_solve": launches, "share_s": us * 1e-6 * launches})
+                     "launches_per_solve": launches, "share_s": us * 1e-6 * launches,
+                     "edge_bytes": edge_bytes, "width": info["width"], "threads": info["threads"]})
         log(f"diamond {W.SCHEME_NAMES[p.scheme]}: {us:.1f} us/launch, {flops / us * 1e-6:.2f} TFLOP/s")
     dom = max(kern, key=lambda k: k["share_s"])
     achieved = dom["flops_per_launch"] / (dom["avg_us"] * 1e-6) / 1e12
+    traffic = measured_traffic(dom["width"], dom["threads"]) if dom["scheme"] == "ks" else None
     roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+                "frac": achieved / PEAK_FP64_TFLOPS, "traffic": traffic,
                 "kernel": f"swept_tile<{dom['scheme']}> diamond", "avg_us": dom["avg_us"],
-                "flops_per_launch": dom["flops_per_launch"]}
+                "flops_per_launch": dom["flops_per_launch"],
+                "algorithmic_bytes_per_launch": dom["edge_bytes"],
+                "traffic_source": TRAFFIC_SUMMARY if traffic is not None else None,
+                "kernel_digest": kernel_digest()}
 
     result = {
         "metric": METRIC, "value": value, "unit": "point-updates/s", "n_gpus": 1,
