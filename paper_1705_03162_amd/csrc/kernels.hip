@@ -69,10 +69,15 @@ __device__ __forceinline__ void level_step(const TileArgs &a, int g, int NW, int
     const int half = a.w >> 1;
     const int lo = __builtin_amdgcn_readfirstlane(half - R * m);
     const int hi = __builtin_amdgcn_readfirstlane(half + R * m);
-    const int base = __builtin_amdgcn_readfirstlane(g & ~63);  // first lane of this wave
-    int lmin, lmax;  // lanes of this wave holding at least one computed point: [lmin, lmax)
-    element_lane_span(P, R, INC, SMOD, lo, hi, base, lmin, lmax);
-    if (!(lmin < 64 && lmax > 0 && lmin < lmax)) return;
+    // first lane of this wave (a one-wave tile is lane 0 onwards)
+    const int base = MULTI ? __builtin_amdgcn_readfirstlane(g & ~63) : 0;
+    if (MULTI) {
+        // lanes of this wave holding at least one computed point: [lmin, lmax); a
+        // one-wave tile always holds some (the computed set is never empty)
+        int lmin, lmax;
+        element_lane_span(P, R, INC, SMOD, lo, hi, base, lmin, lmax);
+        if (!(lmin < 64 && lmax > 0 && lmin < lmax)) return;
+    }
 
     // ext[v][i] holds tile position g P - R + i, ext[v][R + P + i] position g P + P + i.
     static_assert(P >= R || P == 1, "a lane's halo spans at most its neighbours, or one point per lane");
@@ -171,7 +176,7 @@ __device__ __forceinline__ void level_step(const TileArgs &a, int g, int NW, int
         element_lane_bounds(P, R, INC, SMOD, lo, hi, base, k, la, lb);
         in[k] = lane >= la && lane < lb;
     }
-    Sch::template level<P>(dst, ext, ODD, a.c, in);
+    Sch::template level<P, MULTI || Sch::SELECT_ONE_WAVE>(dst, ext, ODD, a.c, in);
 }
 
 // Levels s0 + U, s0 + U + 1, ... of one aligned group (s0 = 1 mod G, so the

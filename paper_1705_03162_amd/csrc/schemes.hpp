@@ -6,6 +6,10 @@
 // the destination row (which, for a final RK2 stage, still carries u^m / Q^m
 // at the same points).  Only points k with in[k] set are written; the others
 // keep their previous contents, which is what lets a tile keep its edges in place.
+// With SEL every point is computed and the written ones are selected afterwards,
+// so the P independent updates form one block the compiler can interleave (hides
+// FP64 latency when few waves are resident); without it each point is a branch,
+// which costs fewer vector instructions when a point is cheap (heat).
 //
 //   Heat  (Appendix B, Eq. Heatdisc):  T' = Fo (T_{i+1} + T_{i-1}) + (1 - 2 Fo) T_i
 //   KS    (Appendix C, Eqs. KSDisc, RKm, RKf): 5-point central differences,
@@ -42,21 +46,28 @@ SW_HD double sw_fabs(double x) { return fabs(x); }
 
 struct Heat {
     static constexpr int R = 1, S = 1, NV = 1;
-    template <int P>
+    static constexpr bool SELECT_ONE_WAVE = false;  // 4 operations per point: branch instead
+    template <int P, bool SEL = true>
     SW_HD static void level(double (&dst)[NV][P], const double (&ext)[NV][P + 2 * R],
                             bool /*predictor*/, const Consts &c, const bool (&in)[P])
     {
+        double val[P];
 #pragma unroll
         for (int k = 0; k < P; ++k) {
             double s = ext[0][k + 2] + ext[0][k];
-            double v = c.fo * s + c.c0 * ext[0][k + 1];
-            if (in[k]) dst[0][k] = v;
+            val[k] = c.fo * s + c.c0 * ext[0][k + 1];
+            if (!SEL && in[k]) dst[0][k] = val[k];
+        }
+        if (SEL) {
+#pragma unroll
+            for (int k = 0; k < P; ++k) dst[0][k] = in[k] ? val[k] : dst[0][k];
         }
     }
 };
 
 struct KS {
     static constexpr int R = 2, S = 2, NV = 1;
+    static constexpr bool SELECT_ONE_WAVE = true;
     // f_i(v) = -((v_{i+1}^2 - v_{i-1}^2)/(4dx) + (v_{i+1} + v_{i-1} - 2v_i)/dx^2
     //           + (v_{i+2} + v_{i-2} - 4(v_{i+1} + v_{i-1}) + 6v_i)/dx^4)
     SW_HD static double rhs(double vm2, double vm1, double v0, double vp1, double vp2,
@@ -67,21 +78,27 @@ struct KS {
         double diff4 = (((vp2 + vm2) - 4.0 * (vp1 + vm1)) + 6.0 * v0) * c.c4;
         return -((advect + diff2) + diff4);
     }
-    template <int P>
+    template <int P, bool SEL = true>
     SW_HD static void level(double (&dst)[NV][P], const double (&ext)[NV][P + 2 * R],
                             bool predictor, const Consts &c, const bool (&in)[P])
     {
+        double val[P];
 #pragma unroll
         for (int k = 0; k < P; ++k) {
             double f = rhs(ext[0][k], ext[0][k + 1], ext[0][k + 2], ext[0][k + 3], ext[0][k + 4], c);
-            double v = predictor ? ext[0][k + 2] + c.hdt * f : dst[0][k] + c.dt * f;
-            if (in[k]) dst[0][k] = v;
+            val[k] = predictor ? ext[0][k + 2] + c.hdt * f : dst[0][k] + c.dt * f;
+            if (!SEL && in[k]) dst[0][k] = val[k];
+        }
+        if (SEL) {
+#pragma unroll
+            for (int k = 0; k < P; ++k) dst[0][k] = in[k] ? val[k] : dst[0][k];
         }
     }
 };
 
 struct Euler {
     static constexpr int R = 2, S = 2, NV = 3;
+    static constexpr bool SELECT_ONE_WAVE = true;
 
     // Eq. EulerP with E the total energy per volume: P = (gamma-1)(E - (m u)/2), u = m/rho.
     SW_HD static double pressure(double rho, double m, double e, const Consts &c)
@@ -131,10 +148,11 @@ struct Euler {
             out[v] = 0.5 * ((fr[v] + fl[v]) + r_sp * (ql[v] - qr[v]));
     }
 
-    template <int P>
+    template <int P, bool SEL = true>
     SW_HD static void level(double (&dst)[NV][P], const double (&ext)[NV][P + 2 * R],
                             bool predictor, const Consts &c, const bool (&in)[P])
     {
+        double val[NV][P];
         double pres[P + 2 * R];
 #pragma unroll
         for (int j = 0; j < P + 2 * R; ++j) pres[j] = pressure(ext[0][j], ext[1][j], ext[2][j], c);
@@ -156,14 +174,19 @@ struct Euler {
             double qc[3] = {ext[0][k + 3], ext[1][k + 3], ext[2][k + 3]};
             double qd[3] = {ext[0][k + 4], ext[1][k + 4], ext[2][k + 4]};
             flux(qa, qb, qc, qd, pres[k + 1], pres[k + 2], pres[k + 3], pres[k + 4], c, fnext);
-            const bool ink = in[k];
 #pragma unroll
             for (int v = 0; v < 3; ++v) {
                 double base = predictor ? ext[v][k + 2] : dst[v][k];
-                double val = base + coef * (fprev[v] - fnext[v]);
-                if (ink) dst[v][k] = val;
+                val[v][k] = base + coef * (fprev[v] - fnext[v]);
+                if (!SEL && in[k]) dst[v][k] = val[v][k];
                 fprev[v] = fnext[v];
             }
+        }
+        if (SEL) {
+#pragma unroll
+            for (int k = 0; k < P; ++k)
+#pragma unroll
+                for (int v = 0; v < 3; ++v) dst[v][k] = in[k] ? val[v][k] : dst[v][k];
         }
     }
 };

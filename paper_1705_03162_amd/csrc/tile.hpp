@@ -261,7 +261,6 @@ SW_HD void lane_store(const TileArgs &a, int64_t j, int g, const double (&r0)[Sc
 // element k of lane l is computed iff la <= l < lb below.
 SW_HD constexpr int group_len(int P, int R) { return P / R < 2 ? 2 : P / R; }
 SW_HD constexpr int pos_mod(int x, int m) { return ((x % m) + m) % m; }
-SW_HD int floor_div_pow2(int x, int P) { return x >= 0 ? x / P : -((-x + P - 1) / P); }
 SW_HD bool level_widening(const TileArgs &a, int s)
 {
     return a.kind == PH_DOWN || (a.kind == PH_DIAMOND && s <= a.H);
@@ -271,7 +270,8 @@ SW_HD void element_lane_bounds(int P, int R, bool widening, int s_mod, int lo, i
 {
     const int ra = pos_mod(widening ? -R * s_mod : R * s_mod, P);  // lo mod P
     const int rb = pos_mod(widening ? R * s_mod : -R * s_mod, P);  // hi mod P
-    const int qa = floor_div_pow2(lo, P) - base, qb = floor_div_pow2(hi, P) - base;
+    // 0 <= lo <= hi <= w (the computed set never leaves the tile): plain shifts
+    const int qa = (int)((unsigned)lo / (unsigned)P) - base, qb = (int)((unsigned)hi / (unsigned)P) - base;
     la = k >= ra ? qa : qa + 1;
     lb = k < rb ? qb + 1 : qb;
 }
@@ -281,8 +281,8 @@ SW_HD void element_lane_span(int P, int R, bool widening, int s_mod, int lo, int
                              int &lmin, int &lmax)
 {
     const int rb = pos_mod(widening ? R * s_mod : -R * s_mod, P);
-    lmin = floor_div_pow2(lo, P) - base;                       // element P-1 is past lo's residue
-    lmax = floor_div_pow2(hi, P) - base + (rb > 0 ? 1 : 0);    // element 0 is below hi's residue
+    lmin = (int)((unsigned)lo / (unsigned)P) - base;                     // element P-1 is past lo's residue
+    lmax = (int)((unsigned)hi / (unsigned)P) - base + (rb > 0 ? 1 : 0);  // element 0 is below hi's residue
 }
 
 // Lane-local bounds [klo, khi) of the points computed at relative level s.
