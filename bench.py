@@ -33,10 +33,12 @@ LOG2N = 20
 NSTEPS = 50_000
 METRIC = "FP64 point-updates/s (swept vs classic, 1 GPU) + batched p50/p99 solve latency"
 PEAK_FP64_TFLOPS = 78.6   # MI355X published FP64 vector peak
+N_SW_ENOTREADY = -6       # include/swept.h: ticket still running
 PEAK_HBM_GBS = 8000.0
-# Algorithmic FP64 operations per point per sub-step level (add/sub/mul/neg-free),
-# as written in the canonical update rules.
-FLOPS_PER_POINT_LEVEL = {W.HEAT: 4, W.KS: 18}
+# Algorithmic FP64 operations per point per sub-step level in the canonical update
+# rules (a fused multiply-add counts 2): heat 1 add + 1 mul + 1 fma; KS 3 add/sub +
+# 2 mul + 6 fma.
+FLOPS_PER_POINT_LEVEL = {W.HEAT: 4, W.KS: 17}
 # Algorithmic HBM bytes per point-update of the classic decomposition (state read
 # and written once per sub-step: heat 8r+8w; KS predictor 8r+8w, final 16r+8w;
 # Euler 3 variables over two sub-steps).
@@ -391,13 +393,24 @@ def served(torch, sw, trace, warmup_s=0.0, max_slots=0):
     with sw.Batch(budget_bytes=200 << 30, max_slots=max_slots, serve=True) as b:
         t0 = time.perf_counter()
         tickets = []
-        for r, x in zip(trace, states):
+        for j, (r, x) in enumerate(zip(trace, states)):
             delay = r.arrival_s - (time.perf_counter() - t0)
             if delay > 0:
                 time.sleep(delay)
             tickets.append(b.submit(r.problem, x))
-        for t in tickets:
-            b.wait(t)
+            if (j + 1) % 2000 == 0:
+                log(f"  submitted {j + 1}/{len(trace)} at {time.perf_counter() - t0:.1f} s")
+        for j, t in enumerate(tickets):
+            while True:   # bounded waits, so a long drain still reports progress
+                try:
+                    b.wait(t, 20_000_000)
+                    break
+                except sw.SweptError as e:
+                    if e.status != N_SW_ENOTREADY:
+                        raise
+                    log(f"  waiting for request {j} at {time.perf_counter() - t0:.1f} s")
+            if (j + 1) % 2000 == 0:
+                log(f"  completed {j + 1}/{len(trace)} at {time.perf_counter() - t0:.1f} s")
         wall = time.perf_counter() - t0
         infos = [b.info(t) for t in tickets]
     keep = [(r, i) for r, i in zip(trace, infos) if r.arrival_s >= warmup_s]
@@ -507,6 +520,10 @@ def main():
                          "anchors: out-of-cache sizes and a copy; serve: configured and sustainable "
                          "serving; oracle: CPU oracle on all cores and one; kernel: counter runs")
     ap.add_argument("--max-steps", type=int, default=50_000)
+    ap.add_argument("--kernel-scheme", default="ks", choices=["ks", "heat"],
+                    help="kernel suite: scheme of the profiled Diamond (N = 2^20)")
+    ap.add_argument("--kernel-width", type=int, default=0, help="kernel suite: tile width (0 = tuned)")
+    ap.add_argument("--kernel-threads", type=int, default=0, help="kernel suite: work-group size (0 = tuned)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the multi-GPU "
@@ -521,12 +538,12 @@ def main():
         dst = torch.empty_like(src)
         dst.copy_(src)
         torch.cuda.synchronize()
-        prob, ic = W.cfg_sweep(W.KS, LOG2N)
-        with sw.Plan(prob) as plan:
+        prob, ic = W.cfg_sweep({"ks": W.KS, "heat": W.HEAT}[args.kernel_scheme], LOG2N)
+        with sw.Plan(prob, args.kernel_width, args.kernel_threads) as plan:
             x = torch.tensor(ic, dtype=torch.float64, device="cuda")
             us = plan.profile_phase(x, kind=1, reps=args.profile_reps)
             info = plan.info()
-        print(json.dumps({"copy_bytes": 2 * src.numel() * 8, "diamond_avg_us": us,
+        print(json.dumps({"copy_bytes": 2 * src.numel() * 8, "diamond_avg_us": us, "scheme": args.kernel_scheme,
                           "width": info["width"], "threads": info["threads"],
                           "levels_per_phase": info["levels_per_phase"], "n": prob.n,
                           "kernel_digest": kernel_digest()}), flush=True)

@@ -4,7 +4,8 @@
  * Test infrastructure only -- see oracle.h.  Every update below is written out
  * from the paper's appendices in the order the equations state it; OpenMP only
  * splits the loop over grid points (no reductions, so the result does not depend
- * on the thread count).  Build with -ffp-contract=off and no fast-math.
+ * on the thread count).  Build with -ffp-contract=off and no fast-math: the
+ * only fused operations are the explicit fma() calls.
  */
 #include "oracle.h"
 
@@ -44,6 +45,8 @@ static double at(const oracle_problem *p, const double *a, int64_t j, int v)
 /* Heat equation, Appendix B, Eq. Heatdisc:                                   */
 /*   T_i^{m+1} = Fo (T_{i+1}^m + T_{i-1}^m) + (1 - 2 Fo) T_i^m,               */
 /*   Fo = alpha dt / dx^2.                                                    */
+/* The product Fo * (sum) and the addition of (1 - 2 Fo) T_i are one fused     */
+/* multiply-add (C99 fma: a single rounding).                                 */
 /* ------------------------------------------------------------------------ */
 
 static void heat_level(const oracle_problem *p, const double *cur, double *nxt,
@@ -53,7 +56,7 @@ static void heat_level(const oracle_problem *p, const double *cur, double *nxt,
 #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; ++i) {
         double s = at(p, cur, i + 1, 0) + at(p, cur, i - 1, 0);
-        nxt[i] = fo * s + c0 * cur[i];
+        nxt[i] = fma(fo, s, c0 * cur[i]);
     }
 }
 
@@ -63,38 +66,47 @@ static void heat_level(const oracle_problem *p, const double *cur, double *nxt,
 /*              + (v_{i+1} + v_{i-1} - 2 v_i)/dx^2                            */
 /*              + (v_{i+2} - 4 v_{i+1} + 6 v_i - 4 v_{i-1} + v_{i-2})/dx^4 )   */
 /* (the central second difference carries -2 v_i), with the four-point       */
-/* terms grouped in symmetric pairs.                                          */
+/* terms grouped in symmetric pairs.  Returned is g = -f, evaluated as:        */
+/*   s1 = v_{i+1} + v_{i-1},  d1 = v_{i+1} - v_{i-1},  s2 = v_{i+2} + v_{i-2}  */
+/*   advect = (d1 s1) c1            (difference of squares, factored)         */
+/*   diff2  = (s1 - 2 v_i) c2                                                 */
+/*   diff4  = ((s2 - 4 s1) + 6 v_i) c4                                        */
+/*   g      = (advect + diff2) + diff4                                        */
+/* with every product that feeds a sum fused into it (C99 fma).  Every step    */
+/* is odd under the mirror v_j -> -v_{-j}, which keeps the scheme's mirror     */
+/* antisymmetry exact in floating point.                                      */
 /* ------------------------------------------------------------------------ */
 
-static double ks_rhs(const oracle_problem *p, const double *v, int64_t i,
-                     double c1, double c2, double c4)
+static double ks_g(const oracle_problem *p, const double *v, int64_t i,
+                   double c1, double c2, double c4)
 {
     double vm2 = at(p, v, i - 2, 0), vm1 = at(p, v, i - 1, 0), v0 = v[i];
     double vp1 = at(p, v, i + 1, 0), vp2 = at(p, v, i + 2, 0);
-    double advect = (vp1 * vp1 - vm1 * vm1) * c1;
-    double diff2 = ((vp1 + vm1) - 2.0 * v0) * c2;
-    double diff4 = (((vp2 + vm2) - 4.0 * (vp1 + vm1)) + 6.0 * v0) * c4;
-    return -((advect + diff2) + diff4);
+    double s1 = vp1 + vm1, d1 = vp1 - vm1, s2 = vp2 + vm2;
+    double diff2 = fma(-2.0, v0, s1) * c2;
+    double advect_diff2 = fma(d1 * s1, c1, diff2);
+    double fourth = fma(6.0, v0, fma(-4.0, s1, s2));
+    return fma(fourth, c4, advect_diff2);
 }
 
-/* Predictor, Eq. RKm: u^{m+1/2} = u^m + (dt/2) f(u^m). */
+/* Predictor, Eq. RKm: u^{m+1/2} = u^m + (dt/2) f(u^m) = u^m - (dt/2) g(u^m). */
 static void ks_predictor(const oracle_problem *p, const double *u, double *half,
                          double c1, double c2, double c4, double hdt)
 {
     const int64_t n = p->n;
 #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; ++i)
-        half[i] = u[i] + hdt * ks_rhs(p, u, i, c1, c2, c4);
+        half[i] = fma(-hdt, ks_g(p, u, i, c1, c2, c4), u[i]);
 }
 
-/* Final, Eq. RKf: u^{m+1} = u^m + dt f(u^{m+1/2}). */
+/* Final, Eq. RKf: u^{m+1} = u^m + dt f(u^{m+1/2}) = u^m - dt g(u^{m+1/2}). */
 static void ks_final(const oracle_problem *p, const double *u, const double *half,
                      double *nxt, double c1, double c2, double c4, double dt)
 {
     const int64_t n = p->n;
 #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; ++i)
-        nxt[i] = u[i] + dt * ks_rhs(p, half, i, c1, c2, c4);
+        nxt[i] = fma(-dt, ks_g(p, half, i, c1, c2, c4), u[i]);
 }
 
 /* ------------------------------------------------------------------------ */

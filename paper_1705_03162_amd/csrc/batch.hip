@@ -65,6 +65,8 @@ struct Ticket {
     Geom geom;
     double *edges = nullptr;
     int32_t phase = 0;
+    int32_t nphases = 0;
+    int64_t admit_tick = -1;   // served: first tick of its group that includes it
 };
 
 int64_t resident_bytes(const sw_problem &p)
@@ -344,33 +346,57 @@ int run_classic_ticket(Ticket &t, hipStream_t st)
 
 // ---------------------------------------------------------------- served mode
 
-// Device tables of one group for one tick (grown on demand).
-struct TickTables {
+// One group (scheme, points per lane) of a served batch.  Each group ticks on
+// its own stream, so a group of short phases advances as often as its launches
+// allow.  Its device table of (solve, tile) items grows by appending admitted
+// solves at tick boundaries and is rebuilt only when more than half of its
+// items belong to finished solves; a device kernel advances every solve's phase
+// after each tick, so no table is re-sent per tick.  Up to two ticks are in
+// flight per group while the host admits, appends and retires.
+struct ServeGroup {
     int scheme = 0, P = 1;
-    SolveDesc *h_desc = nullptr, *d_desc = nullptr;
+    hipStream_t stream = nullptr;
+    SolveDesc *h_desc = nullptr, *d_desc = nullptr;   // pinned staging, device table
     int2 *h_items = nullptr, *d_items = nullptr;
     size_t cap_desc = 0, cap_items = 0;
+    size_t ndesc = 0, nitems = 0, dead_items = 0;
+    std::vector<Ticket *> members;     // desc index -> solve (finished ones stay until a rebuild)
+    std::vector<Ticket *> pending;     // admitted, not yet in the table
+    std::deque<hipEvent_t> inflight;   // completion events of enqueued ticks, oldest first
+    std::vector<hipEvent_t> spare;
+    int64_t enqueued = 0, done = 0;    // ticks
+    int64_t active = 0;                // members still running
     int grid_cap = 1;
-    void ensure(size_t nd, size_t ni)
+
+    static constexpr int kMaxInflight = 2;
+
+    hipError_t init(int sch, int p)
     {
-        if (nd > cap_desc) {
-            size_t c = std::max(nd, 2 * cap_desc);
-            if (h_desc) (void)hipHostFree(h_desc);
-            if (d_desc) (void)hipFree(d_desc);
-            (void)hipHostMalloc((void **)&h_desc, c * sizeof(SolveDesc), 0);
-            (void)hipMalloc(&d_desc, c * sizeof(SolveDesc));
-            cap_desc = c;
-        }
-        if (ni > cap_items) {
-            size_t c = std::max(ni, 2 * cap_items);
-            if (h_items) (void)hipHostFree(h_items);
-            if (d_items) (void)hipFree(d_items);
-            (void)hipHostMalloc((void **)&h_items, c * sizeof(int2), 0);
-            (void)hipMalloc(&d_items, c * sizeof(int2));
-            cap_items = c;
-        }
+        scheme = sch;
+        P = p;
+        grid_cap = batch_blocks_per_cu(sch, p) * num_cus();
+        return hipStreamCreateWithFlags(&stream, hipStreamNonBlocking);
     }
-    void release()
+    // Capacity for nd descriptors and ni items; reallocation waits for the stream
+    // and drops the table contents (the caller rebuilds).
+    hipError_t reserve(size_t nd, size_t ni, bool *reallocated)
+    {
+        *reallocated = false;
+        if (nd <= cap_desc && ni <= cap_items) return hipSuccess;
+        hipError_t e = hipStreamSynchronize(stream);
+        if (e != hipSuccess) return e;
+        release_tables();
+        cap_desc = std::max<size_t>(std::max(nd, 2 * cap_desc), 64);
+        cap_items = std::max<size_t>(std::max(ni, 2 * cap_items), 4096);
+        if ((e = hipHostMalloc((void **)&h_desc, cap_desc * sizeof(SolveDesc), 0)) != hipSuccess) return e;
+        if ((e = hipMalloc(&d_desc, cap_desc * sizeof(SolveDesc))) != hipSuccess) return e;
+        if ((e = hipHostMalloc((void **)&h_items, cap_items * sizeof(int2), 0)) != hipSuccess) return e;
+        if ((e = hipMalloc(&d_items, cap_items * sizeof(int2))) != hipSuccess) return e;
+        ndesc = nitems = dead_items = 0;
+        *reallocated = true;
+        return hipSuccess;
+    }
+    void release_tables()
     {
         if (h_desc) (void)hipHostFree(h_desc);
         if (d_desc) (void)hipFree(d_desc);
@@ -378,99 +404,211 @@ struct TickTables {
         if (d_items) (void)hipFree(d_items);
         h_desc = d_desc = nullptr;
         h_items = d_items = nullptr;
+        cap_desc = cap_items = 0;
+    }
+    void destroy()
+    {
+        if (stream) (void)hipStreamSynchronize(stream);
+        for (hipEvent_t e : inflight) (void)hipEventDestroy(e);
+        for (hipEvent_t e : spare) (void)hipEventDestroy(e);
+        inflight.clear();
+        spare.clear();
+        release_tables();
+        if (stream) (void)hipStreamDestroy(stream);
+        stream = nullptr;
     }
 };
+
+// The phase a solve runs at tick `tick` of its group.
+int32_t phase_at_tick(const Ticket &t, int64_t tick)
+{
+    const int64_t p = tick - t.admit_tick;
+    return (int32_t)std::min<int64_t>(std::max<int64_t>(p, 0), t.nphases);
+}
+
+void write_entries(ServeGroup &g, Ticket *t)
+{
+    SolveDesc d = make_desc(*t);
+    d.phase = phase_at_tick(*t, g.enqueued);
+    const int s = (int)g.ndesc;
+    g.h_desc[g.ndesc++] = d;
+    for (int64_t j = 0; j < t->geom.K; ++j) g.h_items[g.nitems++] = make_int2(s, (int)j);
+}
+
+// Put pending solves into the table before the next tick: append them, or
+// rebuild the table without finished solves (after the stream drains) when
+// those hold more than half of its items or the capacity must grow.
+hipError_t prepare_table(ServeGroup &g)
+{
+    size_t add_d = g.pending.size(), add_i = 0;
+    for (Ticket *t : g.pending) add_i += (size_t)t->geom.K;
+    const bool compact = g.dead_items * 2 > g.nitems && g.dead_items > 0;
+    if (add_d == 0 && !compact) return hipSuccess;
+    for (Ticket *t : g.pending) t->admit_tick = g.enqueued;
+    hipError_t e;
+    bool realloc = false;
+    if (!compact && (e = g.reserve(g.ndesc + add_d, g.nitems + add_i, &realloc)) != hipSuccess) return e;
+    if (!compact && !realloc) {
+        const size_t d0 = g.ndesc, i0 = g.nitems;
+        for (Ticket *t : g.pending) { write_entries(g, t); g.members.push_back(t); }
+        g.pending.clear();
+        // appended ranges only; in-flight ticks read [0, d0) and [0, i0), which stay untouched
+        if ((e = hipMemcpyAsync(g.d_desc + d0, g.h_desc + d0, (g.ndesc - d0) * sizeof(SolveDesc),
+                                hipMemcpyHostToDevice, g.stream)) != hipSuccess) return e;
+        return hipMemcpyAsync(g.d_items + i0, g.h_items + i0, (g.nitems - i0) * sizeof(int2),
+                              hipMemcpyHostToDevice, g.stream);
+    }
+    // rebuild: the staging buffers are rewritten, so nothing may still read them
+    if ((e = hipStreamSynchronize(g.stream)) != hipSuccess) return e;
+    std::vector<Ticket *> keep;
+    size_t nd = add_d, ni = add_i;
+    for (Ticket *t : g.members)
+        if (t->status == SW_TICKET_RUNNING) { keep.push_back(t); ++nd; ni += (size_t)t->geom.K; }
+    if ((e = g.reserve(nd, ni, &realloc)) != hipSuccess) return e;
+    g.ndesc = g.nitems = g.dead_items = 0;
+    g.members.clear();
+    for (Ticket *t : keep) { write_entries(g, t); g.members.push_back(t); }
+    for (Ticket *t : g.pending) { write_entries(g, t); g.members.push_back(t); }
+    g.pending.clear();
+    if ((e = hipMemcpyAsync(g.d_desc, g.h_desc, g.ndesc * sizeof(SolveDesc), hipMemcpyHostToDevice,
+                            g.stream)) != hipSuccess) return e;
+    return hipMemcpyAsync(g.d_items, g.h_items, g.nitems * sizeof(int2), hipMemcpyHostToDevice, g.stream);
+}
+
+hipError_t enqueue_tick(ServeGroup &g)
+{
+    hipError_t e = launch_batch_phase(g.scheme, g.P, g.d_desc, g.d_items, (int64_t)g.nitems, -1,
+                                      (int)std::min<int64_t>((int64_t)g.nitems, g.grid_cap), g.stream);
+    if (e == hipSuccess) e = launch_advance_phases(g.d_desc, (int64_t)g.ndesc, g.stream);
+    if (e != hipSuccess) return e;
+    hipEvent_t ev;
+    if (!g.spare.empty()) { ev = g.spare.back(); g.spare.pop_back(); }
+    else if ((e = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != hipSuccess) return e;
+    if ((e = hipEventRecord(ev, g.stream)) != hipSuccess) { g.spare.push_back(ev); return e; }
+    g.inflight.push_back(ev);
+    g.enqueued += 1;
+    return hipSuccess;
+}
+
+void retire(sw_batch *b, Ticket *t, int32_t status, double t_done)
+{
+    t->status = status;
+    t->t_end = t_done;
+    b->arena.release(t->edges, (size_t)t->geom.edge_doubles * sizeof(double));
+    t->edges = nullptr;
+    b->resident -= t->bytes;
+    b->nresident -= 1;
+}
+
+// Collect finished ticks; solves whose last phase has run are done.  Returns
+// true if anything finished.  Called with b->mu held.
+bool reap(sw_batch *b, ServeGroup &g, hipError_t *err)
+{
+    bool any = false;
+    while (!g.inflight.empty()) {
+        hipError_t q = hipEventQuery(g.inflight.front());
+        if (q == hipErrorNotReady) break;
+        if (q != hipSuccess) { *err = q; break; }
+        g.spare.push_back(g.inflight.front());
+        g.inflight.pop_front();
+        g.done += 1;
+        any = true;
+    }
+    if (!any) return false;
+    const double t_done = now_s();
+    for (Ticket *t : g.members) {
+        if (t->status != SW_TICKET_RUNNING || t->admit_tick + t->nphases > g.done) continue;
+        retire(b, t, SW_TICKET_DONE, t_done);
+        g.dead_items += (size_t)t->geom.K;
+        g.active -= 1;
+    }
+    return true;
+}
+
+void fail_group(sw_batch *b, ServeGroup &g, hipError_t e)
+{
+    const double t = now_s();
+    for (Ticket *x : g.members)
+        if (x->status == SW_TICKET_RUNNING) retire(b, x, SW_TICKET_FAILED, t);
+    for (Ticket *x : g.pending)
+        if (x->status == SW_TICKET_RUNNING) retire(b, x, SW_TICKET_FAILED, t);
+    g.members.clear();
+    g.pending.clear();
+    g.active = 0;
+    g.ndesc = g.nitems = g.dead_items = 0;
+    b->worker_error = hipGetErrorString(e);
+}
 
 void serve_loop(sw_batch *b)
 {
     (void)hipSetDevice(b->device);
-    std::vector<Ticket *> resident;
-    std::map<std::pair<int, int>, TickTables> tables;
+    std::map<std::pair<int, int>, ServeGroup> groups;
     for (;;) {
         std::vector<Ticket *> classic_now;
+        bool stopping = false, busy = false;
         {
-            std::unique_lock<std::mutex> lk(b->mu);
-            for (;;) {
-                // admit in arrival order while memory and slots allow (head-of-line blocking keeps FIFO)
-                while (!b->queue.empty()) {
-                    Ticket *t = find_ticket(b, b->queue.front());
-                    if (!t || t->status != SW_TICKET_QUEUED) { b->queue.pop_front(); continue; }
-                    if (!t->swept) { classic_now.push_back(t); b->queue.pop_front(); continue; }
-                    const bool slots_full = b->cfg.max_slots > 0 && b->nresident >= b->cfg.max_slots;
-                    if (slots_full || b->resident + t->bytes > b->cfg.budget_bytes) break;
-                    t->edges = (double *)b->arena.alloc((size_t)t->geom.edge_doubles * sizeof(double));
-                    if (!t->edges) break;  // retry when memory frees up
-                    t->phase = 0;
-                    t->status = SW_TICKET_RUNNING;
-                    t->t_start = now_s();
-                    b->resident += t->bytes;
-                    b->nresident += 1;
-                    resident.push_back(t);
-                    b->queue.pop_front();
+            std::lock_guard<std::mutex> lk(b->mu);
+            // admit in arrival order while memory and slots allow (head-of-line blocking keeps FIFO)
+            while (!b->queue.empty()) {
+                Ticket *t = find_ticket(b, b->queue.front());
+                if (!t || t->status != SW_TICKET_QUEUED) { b->queue.pop_front(); continue; }
+                if (!t->swept) { classic_now.push_back(t); b->queue.pop_front(); continue; }
+                const bool slots_full = b->cfg.max_slots > 0 && b->nresident >= b->cfg.max_slots;
+                if (slots_full || b->resident + t->bytes > b->cfg.budget_bytes) break;
+                t->edges = (double *)b->arena.alloc((size_t)t->geom.edge_doubles * sizeof(double));
+                if (!t->edges) break;  // retry when memory frees up
+                t->nphases = phase_count(t->geom.Q, t->geom.rem);
+                t->status = SW_TICKET_RUNNING;
+                t->t_start = now_s();
+                b->resident += t->bytes;
+                b->nresident += 1;
+                ServeGroup &g = groups[{t->prob.scheme, t->P}];
+                if (!g.stream) {
+                    hipError_t e = g.init(t->prob.scheme, t->P);
+                    if (e != hipSuccess) { retire(b, t, SW_TICKET_FAILED, now_s()); b->worker_error = hipGetErrorString(e); b->queue.pop_front(); continue; }
                 }
-                if (!resident.empty() || !classic_now.empty()) break;
-                if (b->stop) return;
-                b->cv.wait_for(lk, std::chrono::milliseconds(2));
+                g.pending.push_back(t);
+                g.active += 1;
+                b->queue.pop_front();
             }
+            stopping = b->stop;
         }
         for (Ticket *t : classic_now) {
             (void)run_classic_ticket(*t, b->stream);
             std::lock_guard<std::mutex> lk(b->mu);
             b->cv.notify_all();
         }
-        if (resident.empty()) continue;
-
-        // one tick: every resident solve advances one phase, one launch per group
-        std::map<std::pair<int, int>, std::vector<Ticket *>> groups;
-        for (Ticket *t : resident) groups[{t->prob.scheme, t->P}].push_back(t);
-        hipError_t e = hipSuccess;
+        bool progressed = !classic_now.empty();
         for (auto &kv : groups) {
-            TickTables &tt = tables[kv.first];
-            tt.scheme = kv.first.first;
-            tt.P = kv.first.second;
-            if (tt.grid_cap <= 1) tt.grid_cap = batch_blocks_per_cu(tt.scheme, tt.P) * num_cus();
-            size_t ni = 0;
-            for (Ticket *t : kv.second) ni += (size_t)t->geom.K;
-            tt.ensure(kv.second.size(), ni);
-            size_t k = 0;
-            for (size_t s = 0; s < kv.second.size(); ++s) {
-                tt.h_desc[s] = make_desc(*kv.second[s]);
-                for (int64_t j = 0; j < kv.second[s]->geom.K; ++j) tt.h_items[k++] = make_int2((int)s, (int)j);
+            ServeGroup &g = kv.second;
+            hipError_t e = hipSuccess;
+            {
+                std::lock_guard<std::mutex> lk(b->mu);
+                if (reap(b, g, &e)) { progressed = true; b->ticks += 1; b->cv.notify_all(); }
+                if (e != hipSuccess) { fail_group(b, g, e); b->cv.notify_all(); continue; }
             }
-            if (e == hipSuccess)
-                e = hipMemcpyAsync(tt.d_desc, tt.h_desc, kv.second.size() * sizeof(SolveDesc),
-                                   hipMemcpyHostToDevice, b->stream);
-            if (e == hipSuccess)
-                e = hipMemcpyAsync(tt.d_items, tt.h_items, ni * sizeof(int2), hipMemcpyHostToDevice, b->stream);
-            if (e == hipSuccess)
-                e = launch_batch_phase(tt.scheme, tt.P, tt.d_desc, tt.d_items, (int64_t)ni, -1,
-                                       (int)std::min<int64_t>((int64_t)ni, tt.grid_cap), b->stream);
-        }
-        if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
-        const double t_done = now_s();
-        {
-            std::lock_guard<std::mutex> lk(b->mu);
-            b->ticks += 1;
-            std::vector<Ticket *> still;
-            for (Ticket *t : resident) {
-                t->phase += 1;
-                const bool finished = t->phase >= phase_count(t->geom.Q, t->geom.rem);
-                if (e != hipSuccess || finished) {
-                    t->status = e == hipSuccess ? SW_TICKET_DONE : SW_TICKET_FAILED;
-                    t->t_end = t_done;
-                    b->arena.release(t->edges, (size_t)t->geom.edge_doubles * sizeof(double));
-                    t->edges = nullptr;
-                    b->resident -= t->bytes;
-                    b->nresident -= 1;
-                } else {
-                    still.push_back(t);
+            while ((int)g.inflight.size() < ServeGroup::kMaxInflight && g.active > 0) {
+                e = prepare_table(g);
+                if (e == hipSuccess) e = enqueue_tick(g);
+                if (e != hipSuccess) {
+                    std::lock_guard<std::mutex> lk(b->mu);
+                    fail_group(b, g, e);
+                    b->cv.notify_all();
+                    break;
                 }
+                progressed = true;
             }
-            resident.swap(still);
-            if (e != hipSuccess) b->worker_error = hipGetErrorString(e);
-            b->cv.notify_all();
+            if (!g.inflight.empty() || g.active > 0) busy = true;
+        }
+        if (!busy) {
+            std::unique_lock<std::mutex> lk(b->mu);
+            if (b->queue.empty() && (stopping || b->stop)) break;
+            if (b->queue.empty()) b->cv.wait_for(lk, std::chrono::milliseconds(2));
+        } else if (!progressed) {
+            std::this_thread::sleep_for(std::chrono::microseconds(20));
         }
     }
+    for (auto &kv : groups) kv.second.destroy();
 }
 
 int serve_start(sw_batch *b)

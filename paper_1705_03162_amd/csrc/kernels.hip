@@ -332,6 +332,13 @@ __global__ __launch_bounds__(256) void classic_level(const double *__restrict__ 
     for (int v = 0; v < NV; ++v) dst[(int64_t)v * n + i] = out[v][0];
 }
 
+// Served batches: after a tick, every solve in the table moves to its next phase.
+__global__ void advance_phases(SolveDesc *desc, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n && desc[i].phase < desc[i].nphases) desc[i].phase += 1;
+}
+
 __global__ void stamp_kernel(uint64_t *stamps, int idx)
 {
     if (threadIdx.x == 0) stamps[idx] = wall_clock64();
@@ -455,6 +462,13 @@ int batch_blocks_per_cu(int scheme, int P)
     if (scheme == 0) return batch_occupancy_s<Heat>(P);
     if (scheme == 1) return batch_occupancy_s<KS>(P);
     return batch_occupancy_s<Euler>(P);
+}
+
+hipError_t launch_advance_phases(SolveDesc *desc, int64_t n, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(advance_phases, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, desc, n);
+    return hipGetLastError();
 }
 
 hipError_t launch_stamp(uint64_t *stamps, int idx, hipStream_t st)

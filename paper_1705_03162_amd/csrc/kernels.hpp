@@ -20,6 +20,9 @@ hipError_t launch_classic_level(int scheme, const double *src, double *dst, int6
 hipError_t launch_batch_phase(int scheme, int P, const SolveDesc *desc, const int2 *items, int64_t nitems,
                               int global_phase, int grid, hipStream_t st);
 
+// desc[i].phase += 1 for every solve i < n that has phases left (served ticks).
+hipError_t launch_advance_phases(SolveDesc *desc, int64_t n, hipStream_t st);
+
 // Writes the device wall clock (constant-rate counter) to stamps[idx].
 hipError_t launch_stamp(uint64_t *stamps, int idx, hipStream_t st);
 

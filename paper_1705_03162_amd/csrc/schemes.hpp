@@ -1,5 +1,6 @@
 // Per-point update rules of the three schemes, in one fixed binary64 operation
-// order (no FMA contraction: every file is compiled with -ffp-contract=off).
+// order.  Every file is compiled with -ffp-contract=off, so the only fused
+// multiply-adds are the explicit sw_fma calls (one rounding each, v_fma_f64).
 //
 // Each rule works on a lane-local run of P consecutive points: `ext` holds the
 // source level on those points plus R halo points on each side, `dst` holds
@@ -11,9 +12,12 @@
 // FP64 latency when few waves are resident); without it each point is a branch,
 // which costs fewer vector instructions when a point is cheap (heat).
 //
-//   Heat  (Appendix B, Eq. Heatdisc):  T' = Fo (T_{i+1} + T_{i-1}) + (1 - 2 Fo) T_i
+//   Heat  (Appendix B, Eq. Heatdisc):  T' = Fo (T_{i+1} + T_{i-1}) + (1 - 2 Fo) T_i,
+//         the Fo product fused with the addition
 //   KS    (Appendix C, Eqs. KSDisc, RKm, RKf): 5-point central differences,
-//         predictor u + dt/2 f(u), final u + dt f(u^{m+1/2})
+//         predictor u + dt/2 f(u), final u + dt f(u^{m+1/2}); the advection term
+//         as the factored difference of squares, products fused into the sums
+//         that consume them, every step odd under the mirror v_j -> -v_{-j}
 //   Euler (Appendix D): pressure-ratio limited reconstruction, Roe-averaged
 //         spectral radius, interface flux, same RK2 stages
 #pragma once
@@ -41,6 +45,7 @@ struct Consts {
 };
 
 SW_HD double sw_min(double a, double b) { return a < b ? a : b; }
+SW_HD double sw_fma(double a, double b, double c) { return fma(a, b, c); }
 SW_HD double sw_sqrt(double x) { return sqrt(x); }
 SW_HD double sw_fabs(double x) { return fabs(x); }
 
@@ -55,7 +60,7 @@ struct Heat {
 #pragma unroll
         for (int k = 0; k < P; ++k) {
             double s = ext[0][k + 2] + ext[0][k];
-            val[k] = c.fo * s + c.c0 * ext[0][k + 1];
+            val[k] = sw_fma(c.fo, s, c.c0 * ext[0][k + 1]);
             if (!SEL && in[k]) dst[0][k] = val[k];
         }
         if (SEL) {
@@ -68,15 +73,17 @@ struct Heat {
 struct KS {
     static constexpr int R = 2, S = 2, NV = 1;
     static constexpr bool SELECT_ONE_WAVE = true;
-    // f_i(v) = -((v_{i+1}^2 - v_{i-1}^2)/(4dx) + (v_{i+1} + v_{i-1} - 2v_i)/dx^2
-    //           + (v_{i+2} + v_{i-2} - 4(v_{i+1} + v_{i-1}) + 6v_i)/dx^4)
-    SW_HD static double rhs(double vm2, double vm1, double v0, double vp1, double vp2,
-                            const Consts &c)
+    // g_i(v) = -f_i(v) = (v_{i+1}^2 - v_{i-1}^2)/(4dx) + (v_{i+1} + v_{i-1} - 2v_i)/dx^2
+    //                   + (v_{i+2} + v_{i-2} - 4(v_{i+1} + v_{i-1}) + 6v_i)/dx^4,
+    // the squares as (v_{i+1} - v_{i-1})(v_{i+1} + v_{i-1})
+    SW_HD static double g(double vm2, double vm1, double v0, double vp1, double vp2,
+                          const Consts &c)
     {
-        double advect = (vp1 * vp1 - vm1 * vm1) * c.c1;
-        double diff2 = ((vp1 + vm1) - 2.0 * v0) * c.c2;
-        double diff4 = (((vp2 + vm2) - 4.0 * (vp1 + vm1)) + 6.0 * v0) * c.c4;
-        return -((advect + diff2) + diff4);
+        const double s1 = vp1 + vm1, d1 = vp1 - vm1, s2 = vp2 + vm2;
+        const double diff2 = sw_fma(-2.0, v0, s1) * c.c2;
+        const double advect_diff2 = sw_fma(d1 * s1, c.c1, diff2);
+        const double fourth = sw_fma(6.0, v0, sw_fma(-4.0, s1, s2));
+        return sw_fma(fourth, c.c4, advect_diff2);
     }
     template <int P, bool SEL = true>
     SW_HD static void level(double (&dst)[NV][P], const double (&ext)[NV][P + 2 * R],
@@ -85,8 +92,9 @@ struct KS {
         double val[P];
 #pragma unroll
         for (int k = 0; k < P; ++k) {
-            double f = rhs(ext[0][k], ext[0][k + 1], ext[0][k + 2], ext[0][k + 3], ext[0][k + 4], c);
-            val[k] = predictor ? ext[0][k + 2] + c.hdt * f : dst[0][k] + c.dt * f;
+            const double gk = g(ext[0][k], ext[0][k + 1], ext[0][k + 2], ext[0][k + 3], ext[0][k + 4], c);
+            // u + coef f = u - coef g
+            val[k] = predictor ? sw_fma(-c.hdt, gk, ext[0][k + 2]) : sw_fma(-c.dt, gk, dst[0][k]);
             if (!SEL && in[k]) dst[0][k] = val[k];
         }
         if (SEL) {
