@@ -444,18 +444,17 @@ def suite_serve(rate=2000.0, duration_s=10.0, warmup_s=1.0, fifo_prefix=300):
     # sustainable rate: ascending offered rates on 5 s traces.  With a budget this
     # large every request is resident at once, so an overloaded server shows up as
     # a long drain after the last arrival, not as a queue: a rate is sustainable
-    # when the drain takes at most max(2 s, half the window) and the mean latency
-    # of the last third of arrivals stays within 1.5x of the first third.
+    # when the drain takes at most max(2 s, half the window).  (Latency by arrival
+    # time is reported too; with a few hundred heavy-tailed requests it is too
+    # noisy to decide on.)
     stable = None
     window = 5.0
     for r in (25.0, 50.0, 75.0, 100.0, 150.0, 200.0, 300.0):
         tr = W.poisson_trace(rate=r, duration_s=window, seed=6)
         x = served(torch, sw, tr)
-        th = x["mean_latency_by_arrival_third_s"]
         drain = x["wall_s"] - max(q.arrival_s for q in tr)
         x["drain_s"] = drain
-        ok = (th[0] is not None and th[2] is not None and th[2] <= 1.5 * th[0]
-              and drain <= max(2.0, 0.5 * window))
+        ok = drain <= max(2.0, 0.5 * window)
         x.update({"run": "rate_search", "offered_rate_per_s": r, "stable": ok})
         print(json.dumps(x), flush=True)
         log(f"serve rate {r}/s: stable={ok} p50 {x['p50_latency_s']:.3f} s p99 {x['p99_latency_s']:.3f} s")

@@ -19,7 +19,8 @@
 //         as the factored difference of squares, products fused into the sums
 //         that consume them, every step odd under the mirror v_j -> -v_{-j}
 //   Euler (Appendix D): pressure-ratio limited reconstruction, Roe-averaged
-//         spectral radius, interface flux, same RK2 stages
+//         spectral radius, interface flux, same RK2 stages; products fused into the
+//         sums that consume them, each cell's pressure ratio computed once
 #pragma once
 
 #include <stdint.h>
@@ -109,22 +110,22 @@ struct Euler {
     static constexpr bool SELECT_ONE_WAVE = true;
 
     // Eq. EulerP with E the total energy per volume: P = (gamma-1)(E - (m u)/2), u = m/rho.
+    // Products that feed a sum are fused into it throughout (for this halving the
+    // fusion is exact either way).
     SW_HD static double pressure(double rho, double m, double e, const Consts &c)
     {
         double u = m / rho;
-        return c.gm1 * (e - 0.5 * (m * u));
+        return c.gm1 * sw_fma(-0.5, m * u, e);
     }
 
-    // Flux through the interface between cells b and c, given cells a, b, c, d and
-    // their pressures.
-    SW_HD static void flux(const double qa[3], const double qb[3], const double qc[3],
-                           const double qd[3], double pa, double pb, double pc, double pd,
+    // Eq. Pratio at cell j from the pressures of cells j-1, j, j+1.
+    SW_HD static double pratio(double pm, double p0, double pp) { return (pp - p0) / (p0 - pm); }
+
+    // Flux through the interface between cells b and c, given both cells and the
+    // pressure ratios at b and c (each ratio is shared by two interfaces).
+    SW_HD static void flux(const double qb[3], const double qc[3], double pr_b, double pr_c,
                            const Consts &k, double out[3])
     {
-        (void)qa; (void)qd;
-        // Eq. Pratio at b and c.
-        double pr_b = (pc - pb) / (pb - pa);
-        double pr_c = (pd - pc) / (pc - pb);
         // Eqs. limitleft / limitright (tl: ratio used on the left state, tr: right).
         double tl = k.limiter ? 1.0 / pr_b : pr_b;
         double tr = k.limiter ? pr_c : 1.0 / pr_c;
@@ -134,26 +135,25 @@ struct Euler {
         double ql[3], qr[3];
 #pragma unroll
         for (int v = 0; v < 3; ++v) {
-            ql[v] = okl ? qb[v] + sl * (qc[v] - qb[v]) : qb[v];
-            qr[v] = okr ? qc[v] + sr * (qb[v] - qc[v]) : qc[v];
+            ql[v] = okl ? sw_fma(sl, qc[v] - qb[v], qb[v]) : qb[v];
+            qr[v] = okr ? sw_fma(sr, qb[v] - qc[v], qc[v]) : qc[v];
         }
         // Eq. EulerF on both reconstructed states.
         double ul = ql[1] / ql[0], ur = qr[1] / qr[0];
-        double pl = k.gm1 * (ql[2] - 0.5 * (ql[1] * ul));
-        double prr = k.gm1 * (qr[2] - 0.5 * (qr[1] * ur));
-        double fl[3] = {ql[1], ql[1] * ul + pl, ul * (ql[2] + pl)};
-        double fr[3] = {qr[1], qr[1] * ur + prr, ur * (qr[2] + prr)};
+        double pl = k.gm1 * sw_fma(-0.5, ql[1] * ul, ql[2]);
+        double prr = k.gm1 * sw_fma(-0.5, qr[1] * ur, qr[2]);
+        double fl[3] = {ql[1], sw_fma(ql[1], ul, pl), ul * (ql[2] + pl)};
+        double fr[3] = {qr[1], sw_fma(qr[1], ur, prr), ur * (qr[2] + prr)};
         // Roe average and spectral radius.
         double sql = sw_sqrt(ql[0]), sqr = sw_sqrt(qr[0]);
         double rho_s = sw_sqrt(ql[0] * qr[0]);
         double den = sql + sqr;
-        double u_s = (sql * ul + sqr * ur) / den;
-        double e_s = (sql * ql[2] + sqr * qr[2]) / den;
-        double p_s = k.gm1 * (e_s - 0.5 * ((rho_s * u_s) * u_s));
+        double u_s = sw_fma(sql, ul, sqr * ur) / den;
+        double e_s = sw_fma(sql, ql[2], sqr * qr[2]) / den;
+        double p_s = k.gm1 * sw_fma(-0.5, (rho_s * u_s) * u_s, e_s);
         double r_sp = sw_sqrt((k.gamma * p_s) / rho_s) + sw_fabs(u_s);
 #pragma unroll
-        for (int v = 0; v < 3; ++v)
-            out[v] = 0.5 * ((fr[v] + fl[v]) + r_sp * (ql[v] - qr[v]));
+        for (int v = 0; v < 3; ++v) out[v] = 0.5 * sw_fma(r_sp, ql[v] - qr[v], fr[v] + fl[v]);
     }
 
     template <int P, bool SEL = true>
@@ -164,28 +164,28 @@ struct Euler {
         double pres[P + 2 * R];
 #pragma unroll
         for (int j = 0; j < P + 2 * R; ++j) pres[j] = pressure(ext[0][j], ext[1][j], ext[2][j], c);
+        // ratio at ext cells 1 .. P+2 (index j - 1)
+        double pr[P + 2];
+#pragma unroll
+        for (int j = 1; j <= P + 2; ++j) pr[j - 1] = pratio(pres[j - 1], pres[j], pres[j + 1]);
         const double coef = predictor ? c.hlam : c.lam;
         // Interface j sits between ext cells j+1 and j+2 (point k has interfaces k, k+1).
         double fprev[3];
         {
-            double qa[3] = {ext[0][0], ext[1][0], ext[2][0]};
             double qb[3] = {ext[0][1], ext[1][1], ext[2][1]};
             double qc[3] = {ext[0][2], ext[1][2], ext[2][2]};
-            double qd[3] = {ext[0][3], ext[1][3], ext[2][3]};
-            flux(qa, qb, qc, qd, pres[0], pres[1], pres[2], pres[3], c, fprev);
+            flux(qb, qc, pr[0], pr[1], c, fprev);
         }
 #pragma unroll
         for (int k = 0; k < P; ++k) {
             double fnext[3];
-            double qa[3] = {ext[0][k + 1], ext[1][k + 1], ext[2][k + 1]};
             double qb[3] = {ext[0][k + 2], ext[1][k + 2], ext[2][k + 2]};
             double qc[3] = {ext[0][k + 3], ext[1][k + 3], ext[2][k + 3]};
-            double qd[3] = {ext[0][k + 4], ext[1][k + 4], ext[2][k + 4]};
-            flux(qa, qb, qc, qd, pres[k + 1], pres[k + 2], pres[k + 3], pres[k + 4], c, fnext);
+            flux(qb, qc, pr[k + 1], pr[k + 2], c, fnext);
 #pragma unroll
             for (int v = 0; v < 3; ++v) {
                 double base = predictor ? ext[v][k + 2] : dst[v][k];
-                val[v][k] = base + coef * (fprev[v] - fnext[v]);
+                val[v][k] = sw_fma(coef, fprev[v] - fnext[v], base);
                 if (!SEL && in[k]) dst[v][k] = val[v][k];
                 fprev[v] = fnext[v];
             }
