@@ -12,10 +12,12 @@
  *   SW_EULER  1D Euler, 2nd-order finite volume, limiter, Roe-averaged spectral-radius flux, RK2
  *             (Appendix D)
  *
- * Every solve computes, in IEEE binary64 with no FMA contraction, exactly the
- * classic level-by-level result: the swept rule performs the same operations in
- * a different order and place (Sec. 2).  swept_solve and classic_solve return
- * bit-identical states for the same plan and input.
+ * Every solve computes, in IEEE binary64, exactly the classic level-by-level
+ * result: the swept rule performs the same operations in a different order and
+ * place (Sec. 2).  Each product that the canonical update rules fuse into a sum
+ * is one correctly rounded fused multiply-add; nothing else is contracted.
+ * swept_solve and classic_solve return bit-identical states for the same plan
+ * and input.
  *
  * Conventions
  *  - State layout: caller-owned DEVICE memory, float64, structure of arrays

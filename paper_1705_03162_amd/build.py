@@ -1,8 +1,9 @@
 """Build libswept.so (HIP, gfx950) in-tree with hipcc.
 
 Every translation unit is compiled with -ffp-contract=off and without fast-math
-so that each binary64 operation is rounded exactly as written; that is what
-makes the swept, classic and reference results bit-identical.
+so that each binary64 operation (an explicit fma included) is rounded exactly as
+written; that is what makes the swept, classic and reference results
+bit-identical.
 """
 from __future__ import annotations
 

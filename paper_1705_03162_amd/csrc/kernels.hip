@@ -8,8 +8,9 @@
 // each neighbouring lane; inside a wave they arrive through DPP row moves across
 // the whole wave (wave_shr:1 / wave_shl:1), between waves through a small
 // double-buffered LDS exchange with one barrier per level.  A one-wave tile
-// therefore runs barrier-free.  There is no contraction anywhere, so MFMA has no
-// role; the kernel is bound by FP64 VALU issue.
+// therefore runs barrier-free.  A stencil update is no matrix product, so MFMA
+// has no role; the kernel is bound by FP64 VALU issue (fused multiply-adds where
+// the canonical rules write them, nothing contracted implicitly).
 #include <hip/hip_runtime.h>
 
 #include "kernels.hpp"

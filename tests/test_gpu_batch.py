@@ -105,6 +105,34 @@ def test_served_mix_equals_alone():
         assert np.array_equal(x.cpu().numpy(), alone(prob, ic))
 
 
+def test_served_group_appends_and_compaction():
+    """One (scheme, points per lane) group: 24 heat solves whose n are multiples of 512
+    (eight points per lane for all), uneven step counts, submitted in three bursts.  Later
+    solves join a group that is already ticking (appended to its table) and most solves
+    finish while others still run (the table is rebuilt once half of it is finished);
+    every result equals the solve alone."""
+    rng = np.random.default_rng(11)
+    probs = []
+    for j in range(24):
+        n = 512 * int(rng.integers(1, 9))
+        probs.append((W.heat_problem(n, int(rng.integers(50, 3000))), W.fourier_ic(n, 100 + j)))
+    states = [torch.tensor(ic, dtype=torch.float64, device=DEV) for _, ic in probs]
+    torch.cuda.synchronize()
+    print(f"[gpu] served group of {len(probs)} heat solves in three bursts", flush=True)
+    with sw.Batch(budget_bytes=1 << 33, serve=True) as b:
+        tickets = []
+        for burst in range(3):
+            for (p, _), x in list(zip(probs, states))[8 * burst:8 * burst + 8]:
+                tickets.append(b.submit(p, x))
+            time.sleep(0.02)
+        for t in tickets:
+            b.wait(t, timeout_us=60_000_000)
+        infos = [b.info(t) for t in tickets]
+    assert all(i["status"] == N.SW_TICKET_DONE and i["width"] == 512 for i in infos)
+    for (prob, ic), x in zip(probs, states):
+        assert np.array_equal(x.cpu().numpy(), alone(prob, ic))
+
+
 def test_served_budget_queues_and_cancel():
     big = (W.ks_problem(1 << 16, 3000), W.fourier_ic(1 << 16, 1))
     small = [(W.heat_problem(1024, 200 + j), W.fourier_ic(1024, j)) for j in range(4)]

@@ -177,6 +177,35 @@ def test_full_size_ks_sampled_against_oracle_windows(oracle_mod):
         assert got[0, center] == ref[0, mid], center
 
 
+def test_full_size_sod_n2p20_prefix_swept_equals_classic():
+    """Sod at N = 2^20 (1.15M steps to t = 0.2), the first 20,000 steps in the tuned tile
+    shape: swept == classic bitwise, density and pressure stay positive."""
+    prob, ic = W.cfg_sod(20)
+    prob = prob.with_steps(20_000)
+    swept = gpu_solve(prob, ic, "swept")
+    classic = gpu_solve(prob, ic, "classic")
+    assert np.array_equal(swept, classic)
+    rho, m, e = swept
+    assert (rho > 0).all() and (e - 0.5 * m * m / rho > 0).all()
+
+
+def test_full_size_sod_sampled_against_oracle_windows(oracle_mod):
+    """Sod, N = 2^20, 2,000 steps: a cell after m steps depends only on the 4m cells on
+    each side (two sub-steps of radius 2), so the oracle on a window with the same
+    Dirichlet ends reproduces it exactly; the windows cover both tube ends and the
+    initial discontinuity."""
+    m = 2000
+    prob, ic = W.cfg_sod(20, nsteps=m)
+    got = gpu_solve(prob, ic, "swept")
+    reach = 2 * 2 * m
+    for center in (0, 7, prob.n // 2 - 1, prob.n // 2 + 5, 700_001, prob.n - 1):
+        lo, hi = max(0, center - reach - 8), min(prob.n, center + reach + 9)
+        win = W.Problem(W.EULER, hi - lo, m, prob.dt, prob.dx, bc=W.DIRICHLET, gamma=prob.gamma,
+                        bc_left=prob.bc_left, bc_right=prob.bc_right)
+        ref = oracle_mod.solve(win, ic[:, lo:hi])
+        assert np.array_equal(got[:, center], ref[:, center - lo]), center
+
+
 # ------------------------------------------------------------ invariances
 
 def test_repeat_runs_bitwise_identical():
