@@ -5,6 +5,7 @@ against the oracle, and swept == classic bit for bit on the GPU.  All solves go
 through the C interface (libswept.so) via the ctypes binding.
 """
 import ctypes
+import dataclasses
 
 import numpy as np
 import pytest
@@ -204,6 +205,36 @@ def test_full_size_sod_sampled_against_oracle_windows(oracle_mod):
                         bc_left=prob.bc_left, bc_right=prob.bc_right)
         ref = oracle_mod.solve(win, ic[:, lo:hi])
         assert np.array_equal(got[:, center], ref[:, center - lo]), center
+
+
+def test_largest_size_heat_and_ks_n2p26(oracle_mod):
+    """N = 2^26 (the out-of-cache size the benchmark's anchors use), 300 steps, tuned
+    shapes: swept == classic bitwise, and sampled points equal the oracle run on the
+    window of points they depend on."""
+    n, m = 1 << 26, 300
+    for prob, reach in ((W.heat_problem(n, m), m), (W.ks_problem(n, m), 4 * m)):
+        ic = W.random_ic(n, 1, seed=26 + prob.scheme)
+        swept = gpu_solve(prob, ic, "swept")
+        assert np.array_equal(swept, gpu_solve(prob, ic, "classic"))
+        for center in (0, 12_345_679, n - 1):
+            idx = (center + np.arange(-reach - 4, reach + 5)) % n
+            ref = oracle_mod.solve(dataclasses.replace(prob, n=len(idx)), ic[:, idx])
+            assert swept[0, center] == ref[0, reach + 4], (prob.scheme, center)
+
+
+@pytest.mark.parametrize("scheme", [W.HEAT, W.KS, W.EULER])
+def test_ragged_n_only_narrow_tiles_divide(oracle_mod, scheme):
+    """N = 64 x 12293 (an odd multiple of 64: only the 64-point tile divides it), tuned
+    plan: swept equals the oracle bit for bit."""
+    n = 64 * 12293
+    if scheme == W.EULER:
+        prob, ic = W.sod_problem(n, 150), W.sod_ic(n)
+    else:
+        prob = W.heat_problem(n, 700) if scheme == W.HEAT else W.ks_problem(n, 300)
+        ic = W.fourier_ic(n, seed=5)
+    with sw.Plan(prob) as plan:
+        assert plan.info()["width"] == 64 and plan.info()["swept_ok"] == 1
+    assert np.array_equal(gpu_solve(prob, ic, "swept"), oracle_mod.solve(prob, ic))
 
 
 # ------------------------------------------------------------ invariances
