@@ -68,19 +68,30 @@ int ensure_device(sw_plan *p)
     HIP_TRY(hipGetDevice(&dev));
     const Geom &g = p->geom;
     const size_t state_bytes = (size_t)g.n * g.nv * sizeof(double);
-    if (g.swept_ok && g.edge_doubles > 0) {
-        if (hipMalloc(&p->d_edges, (size_t)g.edge_doubles * sizeof(double)) != hipSuccess) {
-            (void)hipGetLastError();
-            return fail(SW_ENOMEM, "edge buffer allocation failed");
-        }
-    }
-    if (hipMalloc(&p->d_tmp, state_bytes) != hipSuccess) {
+    // on any failure, release what this call allocated so a later call starts clean
+    auto undo = [p](int code, const char *msg) {
         (void)hipGetLastError();
-        return fail(SW_ENOMEM, "classic scratch allocation failed");
-    }
-    HIP_TRY(hipMalloc(&p->d_flag, sizeof(int)));
-    HIP_TRY(hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking));
-    HIP_TRY(hipEventCreateWithFlags(&p->done, hipEventDisableTiming));
+        if (p->done) (void)hipEventDestroy(p->done);
+        if (p->cap) (void)hipStreamDestroy(p->cap);
+        (void)hipFree(p->d_flag);
+        (void)hipFree(p->d_tmp);
+        (void)hipFree(p->d_edges);
+        p->done = nullptr;
+        p->cap = nullptr;
+        p->d_flag = nullptr;
+        p->d_tmp = p->d_edges = nullptr;
+        return fail(code, msg);
+    };
+    if (g.swept_ok && g.edge_doubles > 0 &&
+        hipMalloc(&p->d_edges, (size_t)g.edge_doubles * sizeof(double)) != hipSuccess)
+        return undo(SW_ENOMEM, "edge buffer allocation failed");
+    if (hipMalloc(&p->d_tmp, state_bytes) != hipSuccess)
+        return undo(SW_ENOMEM, "classic scratch allocation failed");
+    if (hipMalloc(&p->d_flag, sizeof(int)) != hipSuccess) return undo(SW_ENOMEM, "flag allocation failed");
+    if (hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking) != hipSuccess)
+        return undo(SW_EDEVICE, "capture stream creation failed");
+    if (hipEventCreateWithFlags(&p->done, hipEventDisableTiming) != hipSuccess)
+        return undo(SW_EDEVICE, "event creation failed");
     p->device = dev;
     return SW_OK;
 }

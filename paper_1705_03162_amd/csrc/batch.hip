@@ -385,16 +385,22 @@ struct ServeGroup {
         if (nd <= cap_desc && ni <= cap_items) return hipSuccess;
         hipError_t e = hipStreamSynchronize(stream);
         if (e != hipSuccess) return e;
+        const size_t cd = std::max<size_t>(std::max(nd, 2 * cap_desc), 64);
+        const size_t ci = std::max<size_t>(std::max(ni, 2 * cap_items), 4096);
         release_tables();
-        cap_desc = std::max<size_t>(std::max(nd, 2 * cap_desc), 64);
-        cap_items = std::max<size_t>(std::max(ni, 2 * cap_items), 4096);
-        if ((e = hipHostMalloc((void **)&h_desc, cap_desc * sizeof(SolveDesc), 0)) != hipSuccess) return e;
-        if ((e = hipMalloc(&d_desc, cap_desc * sizeof(SolveDesc))) != hipSuccess) return e;
-        if ((e = hipHostMalloc((void **)&h_items, cap_items * sizeof(int2), 0)) != hipSuccess) return e;
-        if ((e = hipMalloc(&d_items, cap_items * sizeof(int2))) != hipSuccess) return e;
         ndesc = nitems = dead_items = 0;
         *reallocated = true;
-        return hipSuccess;
+        // capacities are recorded only once every buffer exists
+        if ((e = hipHostMalloc((void **)&h_desc, cd * sizeof(SolveDesc), 0)) == hipSuccess &&
+            (e = hipMalloc(&d_desc, cd * sizeof(SolveDesc))) == hipSuccess &&
+            (e = hipHostMalloc((void **)&h_items, ci * sizeof(int2), 0)) == hipSuccess &&
+            (e = hipMalloc(&d_items, ci * sizeof(int2))) == hipSuccess) {
+            cap_desc = cd;
+            cap_items = ci;
+            return hipSuccess;
+        }
+        release_tables();
+        return e;
     }
     void release_tables()
     {
@@ -527,6 +533,10 @@ bool reap(sw_batch *b, ServeGroup &g, hipError_t *err)
 
 void fail_group(sw_batch *b, ServeGroup &g, hipError_t e)
 {
+    // nothing queued on the group may still write edges that are about to be reused
+    (void)hipStreamSynchronize(g.stream);
+    for (hipEvent_t ev : g.inflight) g.spare.push_back(ev);
+    g.inflight.clear();
     const double t = now_s();
     for (Ticket *x : g.members)
         if (x->status == SW_TICKET_RUNNING) retire(b, x, SW_TICKET_FAILED, t);
