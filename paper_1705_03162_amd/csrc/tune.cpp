@@ -52,7 +52,11 @@ bool tuned_shape(const sw_problem &p, int *width, int *threads)
     std::call_once(g_once, load);
     int lg = 0;
     while (lg < 62 && ((int64_t)1 << (lg + 1)) <= p.n) ++lg;
-    auto it = g_table.find({p.scheme, lg});
+    // the measured size class of n, else the nearest smaller one (beyond the largest
+    // measured class the device is saturated), else the nearest larger one
+    auto it = g_table.end();
+    for (int c = lg; c >= 0 && it == g_table.end(); --c) it = g_table.find({p.scheme, c});
+    for (int c = lg + 1; c <= 62 && it == g_table.end(); ++c) it = g_table.find({p.scheme, c});
     if (it == g_table.end()) return false;
     const int w = it->second.first, t = it->second.second;
     if (w <= 0 || t <= 0 || p.n % w != 0) return false;

@@ -121,6 +121,37 @@ def test_default_shape_divides_n(lib):
         lib.swept_plan_destroy(h)
 
 
+def _table():
+    out = {}
+    with open(os.path.join(ROOT, "paper_1705_03162_amd", "tune_gfx950.txt")) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                s, lg, w, t = (int(x) for x in line.split()[:4])
+                out[(s, lg)] = (w, t)
+    return out
+
+
+def test_tuned_shapes_from_nearest_measured_class(lib):
+    """Sizes the table measured take their row; larger sizes take the largest measured
+    class, smaller ones the smallest, as long as that width divides n."""
+    table = _table()
+    for scheme in (W.HEAT, W.KS, W.EULER):
+        classes = sorted(lg for s, lg in table if s == scheme)
+        for lg, cls in ((classes[-1], classes[-1]), (classes[-1] + 4, classes[-1]),
+                        (classes[0] - 1, classes[0])):
+            n = 1 << lg
+            prob = (W.heat_problem(n, 10) if scheme == W.HEAT else
+                    W.ks_problem(n, 10) if scheme == W.KS else W.sod_problem(n, 10))
+            w, t = table[(scheme, cls)]
+            if n % w:
+                continue
+            rc, h = _plan(lib, prob)
+            assert rc == 0
+            i = _info(lib, h)
+            assert (i.width, i.threads) == (w, t), (scheme, lg)
+            lib.swept_plan_destroy(h)
+
+
 def test_no_legal_width_still_plans_for_classic(lib):
     rc, h = _plan(lib, W.heat_problem(1000, 10))
     assert rc == 0
