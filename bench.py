@@ -35,10 +35,12 @@ METRIC = "FP64 point-updates/s (swept vs classic, 1 GPU) + batched p50/p99 solve
 PEAK_FP64_TFLOPS = 78.6   # MI355X published FP64 vector peak
 N_SW_ENOTREADY = -6       # include/swept.h: ticket still running
 PEAK_HBM_GBS = 8000.0
-# Algorithmic FP64 operations per point per sub-step level in the canonical update
-# rules (a fused multiply-add counts 2): heat 1 add + 1 mul + 1 fma; KS 3 add/sub +
-# 2 mul + 6 fma.
-FLOPS_PER_POINT_LEVEL = {W.HEAT: 4, W.KS: 17}
+# Algorithmic FP64 operations per point per sub-step level: each add, subtract and
+# multiply of the update as the paper writes it, independent of how the kernel
+# fuses or regroups them.  Heat (Eq. Heatdisc): 2 adds, 2 multiplies.  KS (Eq.
+# KSDisc with the four-point terms in symmetric pairs, plus the RK stage): 16 in f,
+# 2 in u + c f.
+FLOPS_PER_POINT_LEVEL = {W.HEAT: 4, W.KS: 18}
 # Algorithmic HBM bytes per point-update of the classic decomposition (state read
 # and written once per sub-step: heat 8r+8w; KS predictor 8r+8w, final 16r+8w;
 # Euler 3 variables over two sub-steps).

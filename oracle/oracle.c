@@ -65,48 +65,47 @@ static void heat_level(const oracle_problem *p, const double *cur, double *nxt,
 /*   f_i(v) = -( (v_{i+1}^2 - v_{i-1}^2)/(4 dx)                               */
 /*              + (v_{i+1} + v_{i-1} - 2 v_i)/dx^2                            */
 /*              + (v_{i+2} - 4 v_{i+1} + 6 v_i - 4 v_{i-1} + v_{i-2})/dx^4 )   */
-/* (the central second difference carries -2 v_i), with the four-point       */
-/* terms grouped in symmetric pairs.  Returned is g = -f, evaluated as:        */
-/*   s1 = v_{i+1} + v_{i-1},  d1 = v_{i+1} - v_{i-1},  s2 = v_{i+2} + v_{i-2}  */
-/*   advect = (d1 s1) c1            (difference of squares, factored)         */
-/*   diff2  = (s1 - 2 v_i) c2                                                 */
-/*   diff4  = ((s2 - 4 s1) + 6 v_i) c4                                        */
-/*   g      = (advect + diff2) + diff4                                        */
-/* with every product that feeds a sum fused into it (C99 fma).  Every step    */
-/* is odd under the mirror v_j -> -v_{-j}, which keeps the scheme's mirror     */
-/* antisymmetry exact in floating point.                                      */
+/* (the central second difference carries -2 v_i).  Returned is g = -f, the   */
+/* same polynomial collected by symmetric stencil pair: with                  */
+/*   s1 = v_{i+1} + v_{i-1},  d1 = v_{i+1} - v_{i-1},  s2 = v_{i+2} + v_{i-2},  */
+/*   c1 = 1/(4 dx), c2 = 1/dx^2, c4 = c2^2,                                   */
+/*   g = c1 d1 s1 + (c2 - 4 c4) s1 + c4 s2 + (6 c4 - 2 c2) v_i,               */
+/* the advection term being the factored difference of squares, evaluated as  */
+/*   g = fma(c1 d1, s1, fma(c2 - 4 c4, s1, fma(c4, s2, (6 c4 - 2 c2) v_i)))    */
+/* (C99 fma, one rounding each).  Every step is odd under the mirror          */
+/* v_j -> -v_{-j}, which keeps the scheme's mirror antisymmetry exact in       */
+/* floating point.                                                            */
 /* ------------------------------------------------------------------------ */
 
-static double ks_g(const oracle_problem *p, const double *v, int64_t i,
-                   double c1, double c2, double c4)
+typedef struct { double c1, c4, k1, k0; } ks_consts;   /* k1 = c2 - 4 c4, k0 = 6 c4 - 2 c2 */
+
+static double ks_g(const oracle_problem *p, const double *v, int64_t i, const ks_consts *k)
 {
     double vm2 = at(p, v, i - 2, 0), vm1 = at(p, v, i - 1, 0), v0 = v[i];
     double vp1 = at(p, v, i + 1, 0), vp2 = at(p, v, i + 2, 0);
     double s1 = vp1 + vm1, d1 = vp1 - vm1, s2 = vp2 + vm2;
-    double diff2 = fma(-2.0, v0, s1) * c2;
-    double advect_diff2 = fma(d1 * s1, c1, diff2);
-    double fourth = fma(6.0, v0, fma(-4.0, s1, s2));
-    return fma(fourth, c4, advect_diff2);
+    double even = fma(k->k1, s1, fma(k->c4, s2, k->k0 * v0));
+    return fma(k->c1 * d1, s1, even);
 }
 
 /* Predictor, Eq. RKm: u^{m+1/2} = u^m + (dt/2) f(u^m) = u^m - (dt/2) g(u^m). */
 static void ks_predictor(const oracle_problem *p, const double *u, double *half,
-                         double c1, double c2, double c4, double hdt)
+                         const ks_consts *k, double hdt)
 {
     const int64_t n = p->n;
 #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; ++i)
-        half[i] = fma(-hdt, ks_g(p, u, i, c1, c2, c4), u[i]);
+        half[i] = fma(-hdt, ks_g(p, u, i, k), u[i]);
 }
 
 /* Final, Eq. RKf: u^{m+1} = u^m + dt f(u^{m+1/2}) = u^m - dt g(u^{m+1/2}). */
 static void ks_final(const oracle_problem *p, const double *u, const double *half,
-                     double *nxt, double c1, double c2, double c4, double dt)
+                     double *nxt, const ks_consts *k, double dt)
 {
     const int64_t n = p->n;
 #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; ++i)
-        nxt[i] = fma(-dt, ks_g(p, half, i, c1, c2, c4), u[i]);
+        nxt[i] = fma(-dt, ks_g(p, half, i, k), u[i]);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -265,13 +264,16 @@ int oracle_solve_timed(const oracle_problem *p, double *state, int nthreads, dou
             double *t = a; a = b; b = t;
         }
     } else if (p->scheme == ORACLE_KS) {
-        double c1 = 1.0 / (4.0 * p->dx);
         double c2 = 1.0 / (p->dx * p->dx);
-        double c4 = c2 * c2;
+        ks_consts k;
+        k.c1 = 1.0 / (4.0 * p->dx);
+        k.c4 = c2 * c2;
+        k.k1 = c2 - 4.0 * k.c4;
+        k.k0 = 6.0 * k.c4 - 2.0 * c2;
         double hdt = 0.5 * p->dt;
         for (int64_t m = 0; m < p->nsteps; ++m) {
-            ks_predictor(p, a, h, c1, c2, c4, hdt);
-            ks_final(p, a, h, b, c1, c2, c4, p->dt);
+            ks_predictor(p, a, h, &k, hdt);
+            ks_final(p, a, h, b, &k, p->dt);
             double *t = a; a = b; b = t;
         }
     } else {

@@ -86,6 +86,8 @@ inline Consts make_consts(const sw_problem &p)
     c.c1 = 1.0 / (4.0 * p.dx);
     c.c2 = 1.0 / (p.dx * p.dx);
     c.c4 = c.c2 * c.c2;
+    c.k1 = c.c2 - 4.0 * c.c4;
+    c.k0 = 6.0 * c.c4 - 2.0 * c.c2;
     c.hdt = 0.5 * p.dt;
     c.dt = p.dt;
     c.gm1 = p.gamma - 1.0;

@@ -15,9 +15,10 @@
 //   Heat  (Appendix B, Eq. Heatdisc):  T' = Fo (T_{i+1} + T_{i-1}) + (1 - 2 Fo) T_i,
 //         the Fo product fused with the addition
 //   KS    (Appendix C, Eqs. KSDisc, RKm, RKf): 5-point central differences,
-//         predictor u + dt/2 f(u), final u + dt f(u^{m+1/2}); the advection term
-//         as the factored difference of squares, products fused into the sums
-//         that consume them, every step odd under the mirror v_j -> -v_{-j}
+//         predictor u + dt/2 f(u), final u + dt f(u^{m+1/2}); f collected by
+//         symmetric stencil pair (the advection term as the factored difference of
+//         squares), products fused into the sums that consume them, every step odd
+//         under the mirror v_j -> -v_{-j}
 //   Euler (Appendix D): pressure-ratio limited reconstruction, Roe-averaged
 //         spectral radius, interface flux, same RK2 stages; products fused into the
 //         sums that consume them, each cell's pressure ratio computed once
@@ -40,6 +41,7 @@ namespace sw {
 struct Consts {
     double fo, c0;                  // heat: Fo = (alpha*dt)/(dx*dx), 1 - 2 Fo
     double c1, c2, c4, hdt, dt;     // KS: 1/(4 dx), 1/dx^2, c2*c2, dt/2, dt
+    double k1, k0;                  // KS: c2 - 4 c4 (pair i+-1), 6 c4 - 2 c2 (point i)
     double gm1, gamma, lam, hlam;   // Euler: gamma-1, gamma, dt/dx, lam/2
     int32_t limiter, pad;           // Euler: 0 ratio as printed, 1 reciprocal
     double ghost_l[3], ghost_r[3];  // Dirichlet ghost values per variable
@@ -76,15 +78,14 @@ struct KS {
     static constexpr bool SELECT_ONE_WAVE = true;
     // g_i(v) = -f_i(v) = (v_{i+1}^2 - v_{i-1}^2)/(4dx) + (v_{i+1} + v_{i-1} - 2v_i)/dx^2
     //                   + (v_{i+2} + v_{i-2} - 4(v_{i+1} + v_{i-1}) + 6v_i)/dx^4,
-    // the squares as (v_{i+1} - v_{i-1})(v_{i+1} + v_{i-1})
+    // collected by symmetric stencil pair (s1 = v_{i+1} + v_{i-1}, d1 = v_{i+1} - v_{i-1},
+    // s2 = v_{i+2} + v_{i-2}): g = c1 d1 s1 + (c2 - 4 c4) s1 + c4 s2 + (6 c4 - 2 c2) v_i
     SW_HD static double g(double vm2, double vm1, double v0, double vp1, double vp2,
                           const Consts &c)
     {
         const double s1 = vp1 + vm1, d1 = vp1 - vm1, s2 = vp2 + vm2;
-        const double diff2 = sw_fma(-2.0, v0, s1) * c.c2;
-        const double advect_diff2 = sw_fma(d1 * s1, c.c1, diff2);
-        const double fourth = sw_fma(6.0, v0, sw_fma(-4.0, s1, s2));
-        return sw_fma(fourth, c.c4, advect_diff2);
+        const double even = sw_fma(c.k1, s1, sw_fma(c.c4, s2, c.k0 * v0));
+        return sw_fma(c.c1 * d1, s1, even);
     }
     template <int P, bool SEL = true>
     SW_HD static void level(double (&dst)[NV][P], const double (&ext)[NV][P + 2 * R],
