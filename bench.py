@@ -523,10 +523,11 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the ensemble and serving runs")
     ap.add_argument("--profile-reps", type=int, default=30)
     ap.add_argument("--suite", default="main",
-                    choices=["main", "sweep", "euler", "ensemble", "serve", "kernel", "anchors", "oracle"],
+                    choices=["main", "sweep", "euler", "ensemble", "serve", "kernel", "classic-kernel",
+                             "anchors", "oracle"],
                     help="main: the one-line benchmark; sweep/euler: per-N swept vs classic lines; "
                          "anchors: out-of-cache sizes and a copy; serve: configured and sustainable "
-                         "serving; oracle: CPU oracle on all cores and one; kernel: counter runs")
+                         "serving; oracle: CPU oracle on all cores and one; kernel, classic-kernel: counter runs")
     ap.add_argument("--max-steps", type=int, default=50_000)
     ap.add_argument("--kernel-scheme", default="ks", choices=["ks", "heat"],
                     help="kernel suite: scheme of the profiled Diamond (N = 2^20)")
@@ -555,6 +556,24 @@ def main():
                           "width": info["width"], "threads": info["threads"],
                           "levels_per_phase": info["levels_per_phase"], "n": prob.n,
                           "kernel_digest": kernel_digest()}), flush=True)
+        return
+    if args.suite == "classic-kernel":
+        # for hardware-counter runs of the classic kernel: a known-size device copy, then
+        # classic solves at an out-of-cache size with one launch per sub-step
+        import torch
+        import paper_1705_03162_amd as sw
+        src = torch.ones(1 << 25, dtype=torch.float64, device="cuda")   # 256 MiB
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        n, steps = 1 << 26, 20
+        for scheme in (W.HEAT, W.KS):
+            prob = (W.heat_problem if scheme == W.HEAT else W.ks_problem)(n, steps)
+            x = device_ic(torch, prob, seed=26)
+            with sw.Plan(prob, flags=sw.SW_TUNE_NO_GRAPH) as plan:
+                plan.classic(x)
+            torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": 2 * src.numel() * 8, "n": n, "steps": steps}), flush=True)
         return
     if args.suite == "anchors":
         suite_anchors()
