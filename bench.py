@@ -314,6 +314,37 @@ def suite_sweep(schemes, log2ns, max_steps):
                 f"stream {rst:.3e} e2e swept {upd / e2e_s:.3e}")
 
 
+def suite_euler_full(log2n=20):
+    """Sod at N = 2^20 for the whole run to t = 0.2 (about 1.15M steps), swept and
+    classic: times, and whether the two final states are bit-identical."""
+    import torch
+    import paper_1705_03162_amd as sw
+    prob, ic = W.cfg_sod(log2n)
+    x0 = torch.tensor(ic, dtype=torch.float64, device="cuda")
+    out = {"suite": "euler-full", "n": prob.n, "steps": prob.nsteps}
+    res = {}
+    for kind in ("swept", "classic"):
+        with sw.Plan(prob) as plan:
+            x = x0.clone()
+            torch.cuda.synchronize()
+            log(f"sod 2^{log2n} full length, {kind} ...")
+            t0 = time.perf_counter()
+            getattr(plan, kind)(x)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            if kind == "swept":
+                out["width"], out["threads"] = plan.info()["width"], plan.info()["threads"]
+        res[kind] = x
+        out[f"{kind}_s"] = dt
+        out[kind] = prob.n * prob.nsteps / dt
+        log(f"  {kind}: {dt:.1f} s, {out[kind]:.3e} point-updates/s")
+    out["bitwise_equal"] = bool(torch.equal(res["swept"], res["classic"]))
+    out["swept_over_classic"] = out["swept"] / out["classic"]
+    rho = res["swept"][0]
+    out["min_density"] = float(rho.min())
+    print(json.dumps(out), flush=True)
+
+
 def device_fourier_ic(torch, n, seed, kmax=16):
     """Smooth periodic field built on the device (same modes as the host generator,
     for sizes where evaluating it on the host would dominate the run)."""
@@ -523,8 +554,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the ensemble and serving runs")
     ap.add_argument("--profile-reps", type=int, default=30)
     ap.add_argument("--suite", default="main",
-                    choices=["main", "sweep", "euler", "ensemble", "serve", "kernel", "classic-kernel",
-                             "anchors", "oracle"],
+                    choices=["main", "sweep", "euler", "euler-full", "ensemble", "serve", "kernel",
+                             "classic-kernel", "anchors", "oracle"],
                     help="main: the one-line benchmark; sweep/euler: per-N swept vs classic lines; "
                          "anchors: out-of-cache sizes and a copy; serve: configured and sustainable "
                          "serving; oracle: CPU oracle on all cores and one; kernel, classic-kernel: counter runs")
@@ -574,6 +605,9 @@ def main():
                 plan.classic(x)
             torch.cuda.synchronize()
         print(json.dumps({"copy_bytes": 2 * src.numel() * 8, "n": n, "steps": steps}), flush=True)
+        return
+    if args.suite == "euler-full":
+        suite_euler_full()
         return
     if args.suite == "anchors":
         suite_anchors()
