@@ -133,6 +133,33 @@ def test_served_group_appends_and_compaction():
         assert np.array_equal(x.cpu().numpy(), alone(prob, ic))
 
 
+def test_served_budget_never_exceeded():
+    """A served batch whose budget holds only a few solves at a time: from every ticket's
+    residency interval [start, end) and its counted bytes (3 n nvars 8), the bytes resident
+    at once never exceed the budget, and every result equals the solve alone."""
+    probs = mixed_problems(24, seed=9, schemes=(W.HEAT, W.KS, W.EULER), nmax=4096, smax=500)
+    sizes = [3 * p.n * p.nvars * 8 for p, _ in probs]
+    budget = 3 * max(sizes)
+    states = [torch.tensor(ic, dtype=torch.float64, device=DEV) for _, ic in probs]
+    torch.cuda.synchronize()
+    with sw.Batch(budget_bytes=budget, serve=True) as b:
+        tickets = [b.submit(p, x) for (p, _), x in zip(probs, states)]
+        for t in tickets:
+            b.wait(t, timeout_us=60_000_000)
+        infos = [b.info(t) for t in tickets]
+    assert all(i["status"] == N.SW_TICKET_DONE for i in infos)
+    events = sorted([(i["start_s"], +sz) for i, sz in zip(infos, sizes)] +
+                    [(i["end_s"], -sz) for i, sz in zip(infos, sizes)], key=lambda e: (e[0], e[1]))
+    held = peak = 0
+    for _, d in events:
+        held += d
+        peak = max(peak, held)
+    assert peak <= budget
+    assert peak > max(sizes)                     # the budget was actually shared
+    for (prob, ic), x in zip(probs, states):
+        assert np.array_equal(x.cpu().numpy(), alone(prob, ic))
+
+
 def test_served_budget_queues_and_cancel():
     big = (W.ks_problem(1 << 16, 3000), W.fourier_ic(1 << 16, 1))
     small = [(W.heat_problem(1024, 200 + j), W.fourier_ic(1024, j)) for j in range(4)]

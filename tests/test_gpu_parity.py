@@ -240,9 +240,22 @@ def test_ragged_n_only_narrow_tiles_divide(oracle_mod, scheme):
 # ------------------------------------------------------------ invariances
 
 def test_repeat_runs_bitwise_identical():
-    prob, ic = W.cfg_sweep(W.KS, 14, nsteps=3000)
-    runs = [gpu_solve(prob, ic, "swept", 1024, 128) for _ in range(3)]
-    assert all(np.array_equal(runs[0], r) for r in runs[1:])
+    """One plan solved 100 times from the same state (multi-wave and one-wave tiles, and the
+    classic path): every result is bit-identical (no races between waves or launches)."""
+    prob, ic = W.cfg_sweep(W.KS, 14, nsteps=600)
+    for width, threads, kind in ((1024, 128, "swept"), (512, 64, "swept"), (0, 0, "classic")):
+        print(f"[gpu] 100 repeats of {kind} w={width} T={threads}", flush=True)
+        with sw.Plan(prob, width, threads) as plan:
+            x0 = torch.tensor(ic, dtype=torch.float64, device=DEV)
+            ref = None
+            for _ in range(100):
+                x = x0.clone()
+                getattr(plan, kind)(x)
+                if ref is None:
+                    ref = x
+                else:
+                    assert torch.equal(x, ref)
+            torch.cuda.synchronize()
 
 
 def test_tile_shape_invariance_bitwise():
