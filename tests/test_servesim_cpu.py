@@ -1,0 +1,244 @@
+"""The batched and served solve scheduler on the CPU.
+
+batch.hip is compiled unchanged against a stand-in runtime (tests/hostsim/fakehip)
+whose streams run lazily -- enqueued work runs only when the host waits for it, so
+ticks are in flight while the scheduler admits, appends and retires -- and whose batch
+kernel runs every (solve, tile) item through the tile emulator.  Every result must equal
+the oracle bit for bit, and the admission rules (memory budget, slot limit, first come
+first served, cancellation) must hold.
+"""
+import ctypes
+import os
+import subprocess
+import time
+
+import numpy as np
+import pytest
+
+import workloads as W
+from paper_1705_03162_amd import _native as N
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HS = os.path.join(ROOT, "tests", "hostsim")
+LIB = os.path.join(HS, "libservesim.so")
+
+
+def _build():
+    subprocess.run(["g++", "-O2", "-std=c++17", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
+                    "-shared", "-pthread", "-Wno-unknown-pragmas", "-Wno-subobject-linkage",
+                    "-I", os.path.join(HS, "fakehip"), "-I", os.path.join(ROOT, "include"),
+                    "-I", os.path.join(ROOT, "paper_1705_03162_amd", "csrc"),
+                    os.path.join(HS, "servesim.cpp"), "-o", LIB], check=True)
+
+
+@pytest.fixture(scope="module")
+def sim():
+    if not os.path.exists(LIB):
+        _build()
+    L = ctypes.CDLL(LIB)
+    for name in ("batch_create", "batch_submit", "batch_run", "batch_poll", "batch_wait",
+                 "batch_cancel", "batch_ticket_info", "batch_destroy"):
+        fn = getattr(L, name)
+        fn.restype, fn.argtypes = N.SIGNATURES[name]
+    L.servesim_ticks.restype = ctypes.c_int64
+    L.servesim_ticks.argtypes = [ctypes.c_void_p]
+    return L
+
+
+class SimBatch:
+    """Host arrays stand in for device memory; the caller keeps them alive."""
+
+    def __init__(self, L, budget, slots=0, serve=False):
+        self.L = L
+        cfg = N.SwBatchConfig(int(budget), int(slots), N.SW_BATCH_SERVE if serve else 0)
+        h = ctypes.c_void_p()
+        assert L.batch_create(ctypes.byref(cfg), ctypes.byref(h)) == 0
+        self.h = h
+        self.keep = []
+
+    def submit(self, prob, state):
+        p = N.problem_struct(prob)
+        t = ctypes.c_uint64()
+        rc = self.L.batch_submit(self.h, ctypes.byref(p), state.ctypes.data, ctypes.byref(t))
+        self.keep.append(p)
+        assert rc == 0, rc
+        return t.value
+
+    def wait(self, t):
+        assert self.L.batch_wait(self.h, t, 120_000_000) == 0
+
+    def wait_all(self, tickets, states):
+        """Wait for each ticket in turn and copy its state the moment it reports done:
+        a finished solve's state must be final then, not only once the batch drains."""
+        snaps = []
+        for t, x in zip(tickets, states):
+            self.wait(t)
+            snaps.append(x.copy())
+        return snaps
+
+    def poll(self, t):
+        s = ctypes.c_int32()
+        assert self.L.batch_poll(self.h, t, ctypes.byref(s)) == 0
+        return s.value
+
+    def info(self, t):
+        i = N.SwTicketInfo()
+        assert self.L.batch_ticket_info(self.h, t, ctypes.byref(i)) == 0
+        return {k: getattr(i, k) for k, _ in N.SwTicketInfo._fields_}
+
+    def close(self):
+        self.L.batch_destroy(self.h)
+
+
+def mixed(count, seed, schemes=(W.HEAT, W.KS, W.EULER), nmax=512, smax=120, bcs=True):
+    rng = np.random.default_rng(seed)
+    out = []
+    for j in range(count):
+        scheme = schemes[int(rng.integers(0, len(schemes)))]
+        n = 64 * int(rng.integers(1, nmax // 64 + 1))
+        steps = int(rng.integers(1, smax))
+        if scheme == W.EULER:
+            prob, ic = W.sod_problem(n, steps), W.sod_ic(n)
+        else:
+            bc = int(rng.integers(0, 3 if scheme == W.HEAT else 2)) if bcs else W.PERIODIC
+            if scheme == W.HEAT:
+                prob = W.heat_problem(n, steps, bc=bc, bc_left=0.25, bc_right=-0.5)
+            else:
+                prob = W.ks_problem(n, steps, bc=bc)
+                if bc == W.DIRICHLET:
+                    prob = W.Problem(W.KS, n, steps, prob.dt, prob.dx, bc=bc, bc_left=(0.3, 0, 0),
+                                     bc_right=(-0.1, 0, 0))
+            ic = W.fourier_ic(n, seed=1000 + j)
+        out.append((prob, np.ascontiguousarray(ic, dtype=np.float64)))
+    return out
+
+
+def nbytes(prob):
+    return 3 * prob.n * prob.nvars * 8
+
+
+def peak_resident(infos, sizes):
+    ev = sorted([(i["start_s"], s) for i, s in zip(infos, sizes)] +
+                [(i["end_s"], -s) for i, s in zip(infos, sizes)], key=lambda e: (e[0], e[1]))
+    held = peak = 0
+    for _, d in ev:
+        held += d
+        peak = max(peak, held)
+    return peak
+
+
+def test_ensemble_equals_oracle(sim, oracle_mod):
+    """Ensemble mode (one captured graph per wave of admitted solves): mixed schemes,
+    sizes and boundaries, each result equal to the oracle."""
+    probs = mixed(14, seed=21)
+    states = [ic.copy() for _, ic in probs]
+    b = SimBatch(sim, budget=1 << 30)
+    tickets = [b.submit(p, x) for (p, _), x in zip(probs, states)]
+    assert sim.batch_run(b.h, None) == 0
+    assert all(b.poll(t) == N.SW_TICKET_DONE for t in tickets)
+    b.close()
+    for (prob, ic), x in zip(probs, states):
+        assert np.array_equal(x, oracle_mod.solve(prob, ic)), (prob.scheme, prob.n, prob.nsteps, prob.bc)
+
+
+def test_ensemble_budget_waves(sim, oracle_mod):
+    """A budget of two solves: the ensemble runs in waves, results unchanged."""
+    probs = mixed(8, seed=22, schemes=(W.HEAT, W.KS))
+    states = [ic.copy() for _, ic in probs]
+    b = SimBatch(sim, budget=2 * max(nbytes(p) for p, _ in probs), slots=2)
+    tickets = [b.submit(p, x) for (p, _), x in zip(probs, states)]
+    assert sim.batch_run(b.h, None) == 0
+    assert all(b.poll(t) == N.SW_TICKET_DONE for t in tickets)
+    b.close()
+    for (prob, ic), x in zip(probs, states):
+        assert np.array_equal(x, oracle_mod.solve(prob, ic))
+
+
+def test_served_equals_oracle_under_budget(sim, oracle_mod):
+    """Served mode with room for about three solves: admissions wait for retirements,
+    the resident bytes never exceed the budget, every result equals the oracle."""
+    probs = mixed(16, seed=23)
+    sizes = [nbytes(p) for p, _ in probs]
+    budget = 3 * max(sizes)
+    states = [ic.copy() for _, ic in probs]
+    b = SimBatch(sim, budget=budget, serve=True)
+    tickets = [b.submit(p, x) for (p, _), x in zip(probs, states)]
+    snaps = b.wait_all(tickets, states)
+    infos = [b.info(t) for t in tickets]
+    ticks = sim.servesim_ticks(b.h)
+    b.close()
+    assert all(i["status"] == N.SW_TICKET_DONE for i in infos)
+    assert ticks > 0
+    assert max(sizes) < peak_resident(infos, sizes) <= budget
+    for (prob, ic), x in zip(probs, snaps):
+        assert np.array_equal(x, oracle_mod.solve(prob, ic)), (prob.scheme, prob.n, prob.nsteps, prob.bc)
+
+
+def test_served_bursts_into_running_groups(sim, oracle_mod):
+    """Solves of one group (heat, n a multiple of 512: eight points per lane) arrive in
+    bursts while earlier ones tick: later solves are appended to a table that in-flight
+    ticks still read, and finished solves are dropped once they fill half of it."""
+    rng = np.random.default_rng(24)
+    probs = [(W.heat_problem(512 * int(rng.integers(1, 3)), int(rng.integers(20, 400))),) for _ in range(18)]
+    probs = [(p, np.ascontiguousarray(W.fourier_ic(p.n, 2000 + j))) for j, (p,) in enumerate(probs)]
+    states = [ic.copy() for _, ic in probs]
+    b = SimBatch(sim, budget=1 << 30, serve=True)
+    tickets = []
+    for burst in range(3):
+        for (p, _), x in list(zip(probs, states))[6 * burst:6 * burst + 6]:
+            tickets.append(b.submit(p, x))
+        time.sleep(0.05)
+    snaps = b.wait_all(tickets, states)
+    infos = [b.info(t) for t in tickets]
+    b.close()
+    assert all(i["status"] == N.SW_TICKET_DONE and i["width"] == 512 for i in infos)
+    for (prob, ic), x in zip(probs, snaps):
+        assert np.array_equal(x, oracle_mod.solve(prob, ic))
+
+
+def test_served_one_slot_is_first_come_first_served(sim, oracle_mod):
+    """With one slot, solves run one after another in submission order."""
+    probs = mixed(6, seed=25, schemes=(W.HEAT, W.KS), smax=60)
+    states = [ic.copy() for _, ic in probs]
+    b = SimBatch(sim, budget=1 << 30, slots=1, serve=True)
+    tickets = [b.submit(p, x) for (p, _), x in zip(probs, states)]
+    snaps = b.wait_all(tickets, states)
+    infos = [b.info(t) for t in tickets]
+    b.close()
+    for prev, cur in zip(infos, infos[1:]):
+        assert cur["start_s"] >= prev["end_s"]
+    for (prob, ic), x in zip(probs, snaps):
+        assert np.array_equal(x, oracle_mod.solve(prob, ic))
+
+
+def test_served_cancel_while_queued(sim, oracle_mod):
+    """A budget of one solve: a queued solve can be cancelled and stays untouched; the
+    others complete."""
+    probs = [(W.ks_problem(256, 300 + 50 * j), np.ascontiguousarray(W.fourier_ic(256, 3000 + j)))
+             for j in range(3)]
+    states = [ic.copy() for _, ic in probs]
+    b = SimBatch(sim, budget=nbytes(probs[0][0]), serve=True)   # exactly one resident solve
+    tickets = [b.submit(p, x) for (p, _), x in zip(probs, states)]
+    assert sim.batch_cancel(b.h, tickets[2]) == 0
+    snaps = b.wait_all(tickets[:2], states[:2])
+    b.wait(tickets[2])
+    status = [b.poll(t) for t in tickets]
+    b.close()
+    assert status == [N.SW_TICKET_DONE, N.SW_TICKET_DONE, N.SW_TICKET_CANCELLED]
+    assert np.array_equal(states[2], probs[2][1])
+    for (prob, ic), x in zip(probs[:2], snaps):
+        assert np.array_equal(x, oracle_mod.solve(prob, ic))
+
+
+def test_served_done_means_final(sim, oracle_mod):
+    """Solves whose ticks take long on the emulator: when a ticket reports done, its
+    state already holds the final level (not only after the batch drains)."""
+    probs = [(W.ks_problem(4096, 150 + 20 * j), np.ascontiguousarray(W.fourier_ic(4096, 4000 + j)))
+             for j in range(3)]
+    states = [ic.copy() for _, ic in probs]
+    b = SimBatch(sim, budget=1 << 30, serve=True)
+    tickets = [b.submit(p, x) for (p, _), x in zip(probs, states)]
+    snaps = b.wait_all(tickets, states)
+    b.close()
+    for (prob, ic), x in zip(probs, snaps):
+        assert np.array_equal(x, oracle_mod.solve(prob, ic))
