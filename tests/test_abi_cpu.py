@@ -202,3 +202,18 @@ def test_strerror_strings(lib):
 def test_destroy_null_is_noop(lib):
     lib.swept_plan_destroy(None)
     lib.batch_destroy(None)
+
+
+def test_binding_rejects_bad_state_before_the_library(lib):
+    """The C interface takes a bare pointer, so the binding checks the tensor first:
+    type, dtype, device, contiguity and size (no kernel can run on a wrong buffer)."""
+    torch = pytest.importorskip("torch")
+    import paper_1705_03162_amd as sw
+    prob = W.heat_problem(1024, 10)
+    with sw.Plan(prob, 64, 64) as plan:
+        with pytest.raises(TypeError):
+            plan.swept([0.0] * 1024)
+        with pytest.raises(ValueError):
+            plan.swept(torch.zeros(1024, dtype=torch.float64))          # host tensor
+        with pytest.raises(ValueError):
+            plan.classic(torch.zeros(1024, dtype=torch.float32))        # wrong dtype
