@@ -70,11 +70,15 @@ static void heat_level(const oracle_problem *p, const double *cur, double *nxt,
 /*   s1 = v_{i+1} + v_{i-1},  d1 = v_{i+1} - v_{i-1},  s2 = v_{i+2} + v_{i-2},  */
 /*   c1 = 1/(4 dx), c2 = 1/dx^2, c4 = c2^2,                                   */
 /*   g = c1 d1 s1 + (c2 - 4 c4) s1 + c4 s2 + (6 c4 - 2 c2) v_i,               */
-/* the advection term being the factored difference of squares, evaluated as  */
-/*   g = fma(c1 d1, s1, fma(c2 - 4 c4, s1, fma(c4, s2, (6 c4 - 2 c2) v_i)))    */
+/* the advection term being the factored difference of squares; the two      */
+/* terms of the i+-1 pair share the factor s1,                                */
+/*   g = s1 (c1 d1 + c2 - 4 c4) + c4 s2 + (6 c4 - 2 c2) v_i,                  */
+/* evaluated as                                                               */
+/*   g = fma(s1, fma(c1, d1, c2 - 4 c4), fma(c4, s2, (6 c4 - 2 c2) v_i))      */
 /* (C99 fma, one rounding each).  Every step is odd under the mirror          */
-/* v_j -> -v_{-j}, which keeps the scheme's mirror antisymmetry exact in       */
-/* floating point.                                                            */
+/* v_j -> -v_{-j} (d1 is even there, s1, s2 and v_i odd), which keeps the     */
+/* scheme's mirror antisymmetry exact in floating point; for a constant state */
+/* d1 = 0 and the pair factor is exactly c2 - 4 c4.                           */
 /* ------------------------------------------------------------------------ */
 
 typedef struct { double c1, c4, k1, k0; } ks_consts;   /* k1 = c2 - 4 c4, k0 = 6 c4 - 2 c2 */
@@ -84,8 +88,8 @@ static double ks_g(const oracle_problem *p, const double *v, int64_t i, const ks
     double vm2 = at(p, v, i - 2, 0), vm1 = at(p, v, i - 1, 0), v0 = v[i];
     double vp1 = at(p, v, i + 1, 0), vp2 = at(p, v, i + 2, 0);
     double s1 = vp1 + vm1, d1 = vp1 - vm1, s2 = vp2 + vm2;
-    double even = fma(k->k1, s1, fma(k->c4, s2, k->k0 * v0));
-    return fma(k->c1 * d1, s1, even);
+    double pair = fma(k->c1, d1, k->k1);
+    return fma(s1, pair, fma(k->c4, s2, k->k0 * v0));
 }
 
 /* Predictor, Eq. RKm: u^{m+1/2} = u^m + (dt/2) f(u^m) = u^m - (dt/2) g(u^m). */

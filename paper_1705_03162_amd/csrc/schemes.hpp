@@ -17,8 +17,9 @@
 //   KS    (Appendix C, Eqs. KSDisc, RKm, RKf): 5-point central differences,
 //         predictor u + dt/2 f(u), final u + dt f(u^{m+1/2}); f collected by
 //         symmetric stencil pair (the advection term as the factored difference of
-//         squares), products fused into the sums that consume them, every step odd
-//         under the mirror v_j -> -v_{-j}
+//         squares, sharing the factor v_{i+1} + v_{i-1} with the second and fourth
+//         differences), products fused into the sums that consume them, every step
+//         odd under the mirror v_j -> -v_{-j}
 //   Euler (Appendix D): pressure-ratio limited reconstruction, Roe-averaged
 //         spectral radius, interface flux, same RK2 stages; products fused into the
 //         sums that consume them, each cell's pressure ratio computed once
@@ -79,13 +80,15 @@ struct KS {
     // g_i(v) = -f_i(v) = (v_{i+1}^2 - v_{i-1}^2)/(4dx) + (v_{i+1} + v_{i-1} - 2v_i)/dx^2
     //                   + (v_{i+2} + v_{i-2} - 4(v_{i+1} + v_{i-1}) + 6v_i)/dx^4,
     // collected by symmetric stencil pair (s1 = v_{i+1} + v_{i-1}, d1 = v_{i+1} - v_{i-1},
-    // s2 = v_{i+2} + v_{i-2}): g = c1 d1 s1 + (c2 - 4 c4) s1 + c4 s2 + (6 c4 - 2 c2) v_i
+    // s2 = v_{i+2} + v_{i-2}), the advection term and the i+-1 pair sharing the factor s1:
+    // g = s1 (c1 d1 + c2 - 4 c4) + c4 s2 + (6 c4 - 2 c2) v_i -- seven operations, the
+    // pair factor one fused multiply-add
     SW_HD static double g(double vm2, double vm1, double v0, double vp1, double vp2,
                           const Consts &c)
     {
         const double s1 = vp1 + vm1, d1 = vp1 - vm1, s2 = vp2 + vm2;
-        const double even = sw_fma(c.k1, s1, sw_fma(c.c4, s2, c.k0 * v0));
-        return sw_fma(c.c1 * d1, s1, even);
+        const double pair = sw_fma(c.c1, d1, c.k1);
+        return sw_fma(s1, pair, sw_fma(c.c4, s2, c.k0 * v0));
     }
     template <int P, bool SEL = true>
     SW_HD static void level(double (&dst)[NV][P], const double (&ext)[NV][P + 2 * R],
