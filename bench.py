@@ -48,8 +48,9 @@ CLASSIC_BYTES_PER_UPDATE = {W.HEAT: 16, W.KS: 40, W.EULER: 120}
 
 # Sources that determine the swept tile kernel's machine code, and the committed
 # hardware-counter summary of its KS Diamond launch at N = 2^20.
-KERNEL_SOURCES = ("paper_1705_03162_amd/csrc/kernels.hip", "paper_1705_03162_amd/csrc/tile.hpp",
-                  "paper_1705_03162_amd/csrc/schemes.hpp", "paper_1705_03162_amd/build.py")
+KERNEL_SOURCES = ("paper_1705_03162_amd/csrc/swept_tile.hpp", "paper_1705_03162_amd/csrc/tiles_ks.hip",
+                  "paper_1705_03162_amd/csrc/tile.hpp", "paper_1705_03162_amd/csrc/schemes.hpp",
+                  "paper_1705_03162_amd/build.py")
 TRAFFIC_SUMMARY = "profiles/swept_tile_ks_diamond_n2p20_pmc.txt"
 
 

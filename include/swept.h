@@ -82,8 +82,9 @@ typedef struct {
     uint32_t reserved;     /* must be 0 */
 } sw_problem;
 
-/* Tile shape.  threads = work-group size (a multiple of 64, at most 1024);
- * width = points per swept tile = points_per_lane * threads, with
+/* Tile shape.  threads = work-group size (a multiple of 64, at most 1024; at
+ * most 512 with 8 or more points per lane, Euler: 512, and 256 with 8 points per
+ * lane); width = points per swept tile = points_per_lane * threads, with
  * points_per_lane in {1, 2, 4, 8, 16} and at least the stencil radius (Euler:
  * at most 8).  Zeros ask for the tuned or default choice. */
 #define SW_TUNE_NO_GRAPH  1   /* enqueue kernels one by one instead of replaying a HIP graph */

@@ -1,16 +1,8 @@
-// HIP kernels for gfx950: the swept tile kernel (Up / Diamond / Down phases)
-// and the classic one-sub-step-per-launch kernel.
-//
-// Swept tile kernel.  One work-group is one node of the swept rule (the paper's
-// Shared variant maps a node to a block, Sec. 4.1), but the two-row working
-// array lives in VGPRs instead of shared memory: lane g owns P consecutive
-// points of both rows.  Per level a lane needs r points of the source row from
-// each neighbouring lane; inside a wave they arrive through DPP row moves across
-// the whole wave (wave_shr:1 / wave_shl:1), between waves through a small
-// double-buffered LDS exchange with one barrier per level.  A one-wave tile
-// therefore runs barrier-free.  A stencil update is no matrix product, so MFMA
-// has no role; the kernel is bound by FP64 VALU issue (fused multiply-adds where
-// the canonical rules write them, nothing contracted implicitly).
+// HIP kernels for gfx950 besides the swept tile kernel: the classic
+// one-sub-step-per-launch kernel, the served-batch phase counter, the device
+// clock stamp and the non-finite scan, plus the dispatch of every launch by
+// scheme.  The swept tile kernel and its batched form are in swept_tile.hpp,
+// instantiated per scheme in tiles_heat.hip, tiles_ks.hip and tiles_euler.hip.
 #include <hip/hip_runtime.h>
 
 #include "kernels.hpp"
@@ -18,284 +10,6 @@
 namespace sw {
 
 namespace {
-
-constexpr int DPP_WAVE_SHL1 = 0x130;  // lane i receives lane i+1
-constexpr int DPP_WAVE_SHR1 = 0x138;  // lane i receives lane i-1
-
-// Zero-filling DPP move: lanes whose source lies outside the wave read 0.
-template <int CTRL>
-__device__ __forceinline__ double dpp_zero(double v)
-{
-    const unsigned long long x = __builtin_bit_cast(unsigned long long, v);
-    const int lo = __builtin_amdgcn_mov_dpp((int)(unsigned)x, CTRL, 0xF, 0xF, true);
-    const int hi = __builtin_amdgcn_mov_dpp((int)(unsigned)(x >> 32), CTRL, 0xF, 0xF, true);
-    const unsigned long long r = ((unsigned long long)(unsigned)hi << 32) | (unsigned long long)(unsigned)lo;
-    return __builtin_bit_cast(double, r);
-}
-
-// One level of a tile: gather the source row with halos, then update the points
-// of the computed set [w/2 - r m, w/2 + r m).  Element k of the wave's lanes is
-// inside for a contiguous range of lanes whose ends take only two values each
-// over k (their residues are compile-time), so a level needs four lane compares
-// however many points a lane holds.  A wave with no point inside skips the level
-// (after publishing its boundary values for its neighbours), which recovers most
-// of the idle half of a triangle in multi-wave tiles.
-template <class Sch, int P, bool ODD, bool MULTI, bool WALL, bool INC, int SMOD>
-__device__ __forceinline__ void level_step(const TileArgs &a, int g, int NW, int s, int m,
-                                           const double (&src)[Sch::NV][P], double (&dst)[Sch::NV][P],
-                                           const double (&hl)[Sch::NV][Sch::R],
-                                           const double (&hr)[Sch::NV][Sch::R],
-                                           double (*xch)[16][2][Sch::NV][Sch::R])
-{
-    constexpr int NV = Sch::NV, R = Sch::R;
-    const int lane = g & 63, wave = g >> 6, buf = s & 1;
-    if (MULTI) {
-        // publish this wave's first and last R points (wave positions p = lane P + k)
-        if (lane * P < R) {
-#pragma unroll
-            for (int v = 0; v < NV; ++v)
-#pragma unroll
-                for (int k = 0; k < P; ++k)
-                    if (lane * P + k < R) xch[buf][wave][0][v][lane * P + k] = src[v][k];
-        }
-        if (lane * P + P > 64 * P - R) {
-#pragma unroll
-            for (int v = 0; v < NV; ++v)
-#pragma unroll
-                for (int k = 0; k < P; ++k)
-                    if (lane * P + k >= 64 * P - R) xch[buf][wave][1][v][lane * P + k - (64 * P - R)] = src[v][k];
-        }
-        __syncthreads();
-    }
-    const int half = a.w >> 1;
-    const int lo = __builtin_amdgcn_readfirstlane(half - R * m);
-    const int hi = __builtin_amdgcn_readfirstlane(half + R * m);
-    // first lane of this wave (a one-wave tile is lane 0 onwards)
-    const int base = MULTI ? __builtin_amdgcn_readfirstlane(g & ~63) : 0;
-    if (MULTI) {
-        // lanes of this wave holding at least one computed point: [lmin, lmax); a
-        // one-wave tile always holds some (the computed set is never empty)
-        int lmin, lmax;
-        element_lane_span(P, R, INC, SMOD, lo, hi, base, lmin, lmax);
-        if (!(lmin < 64 && lmax > 0 && lmin < lmax)) return;
-    }
-
-    // ext[v][i] holds tile position g P - R + i, ext[v][R + P + i] position g P + P + i.
-    static_assert(P >= R || P == 1, "a lane's halo spans at most its neighbours, or one point per lane");
-    double ext[NV][P + 2 * R];
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
-#pragma unroll
-        for (int k = 0; k < P; ++k) ext[v][R + k] = src[v][k];
-        if constexpr (P >= R) {
-#pragma unroll
-            for (int i = 0; i < R; ++i) {
-                ext[v][i] = dpp_zero<DPP_WAVE_SHR1>(src[v][P - R + i]);
-                ext[v][R + P + i] = dpp_zero<DPP_WAVE_SHL1>(src[v][i]);
-            }
-        } else {  // one point per lane: points further away pass through successive lanes
-            ext[v][R - 1] = dpp_zero<DPP_WAVE_SHR1>(src[v][0]);
-#pragma unroll
-            for (int i = R - 2; i >= 0; --i) ext[v][i] = dpp_zero<DPP_WAVE_SHR1>(ext[v][i + 1]);
-            ext[v][R + 1] = dpp_zero<DPP_WAVE_SHL1>(src[v][0]);
-#pragma unroll
-            for (int i = 1; i < R; ++i) ext[v][R + 1 + i] = dpp_zero<DPP_WAVE_SHL1>(ext[v][R + i]);
-        }
-    }
-    const int x0 = g * P;  // first tile position of this lane
-    // The tile's outer halo is read by the widest level of a Diamond/Down only.
-    if (s == a.H && a.kind != PH_UP) {
-        const bool refl = a.bc == BC_REFLECTIVE;  // heat only: R == 1
-        if (x0 < R) {
-            if (refl && (a.ends & 1)) {
-                if constexpr (R == 1)
-                    if (x0 == 0) ext[0][0] = ext[0][mirror_left_src(R, 0)];
-            } else {
-#pragma unroll
-                for (int v = 0; v < NV; ++v)
-#pragma unroll
-                    for (int i = 0; i < R; ++i)
-                        if (x0 - R + i < 0) ext[v][i] = hl[v][x0 + i];
-            }
-        }
-        if (x0 + P + R > a.w) {
-            if (refl && (a.ends & 2)) {
-                if constexpr (R == 1)
-                    if (x0 + P == a.w) ext[0][R + P] = ext[0][mirror_right_src(P, R, 0)];
-            } else {
-#pragma unroll
-                for (int v = 0; v < NV; ++v)
-#pragma unroll
-                    for (int i = 0; i < R; ++i)
-                        if (x0 + P + i >= a.w) ext[v][R + P + i] = hr[v][x0 + P + i - a.w];
-            }
-        }
-    }
-    if (MULTI) {
-        if (lane * P < R && wave > 0) {
-#pragma unroll
-            for (int v = 0; v < NV; ++v)
-#pragma unroll
-                for (int i = 0; i < R; ++i)
-                    if (lane * P - R + i < 0) ext[v][i] = xch[buf][wave - 1][1][v][lane * P + i];
-        }
-        if (lane * P + P + R > 64 * P && wave < NW - 1) {
-#pragma unroll
-            for (int v = 0; v < NV; ++v)
-#pragma unroll
-                for (int i = 0; i < R; ++i)
-                    if (lane * P + P + i >= 64 * P)
-                        ext[v][R + P + i] = xch[buf][wave + 1][0][v][lane * P + P + i - 64 * P];
-        }
-    }
-    if (WALL && a.bc == BC_REFLECTIVE) {  // insulated ends meet at the tile centre (heat, R == 1)
-        if constexpr (R == 1) {
-            if (x0 == half) ext[0][0] = ext[0][mirror_left_src(R, 0)];
-            if (x0 + P == half) ext[0][R + P] = ext[0][mirror_right_src(P, R, 0)];
-        }
-    } else if (WALL) {  // Dirichlet wall at the tile centre: across it lie the ghost values
-        if (x0 >= half && x0 - R < half) {
-#pragma unroll
-            for (int v = 0; v < NV; ++v)
-#pragma unroll
-                for (int i = 0; i < R; ++i)
-                    if (x0 - R + i < half) ext[v][i] = a.c.ghost_l[v];
-        }
-        if (x0 < half && x0 + P + R > half) {
-#pragma unroll
-            for (int v = 0; v < NV; ++v)
-#pragma unroll
-                for (int i = 0; i < R; ++i)
-                    if (x0 + P + i >= half) ext[v][R + P + i] = a.c.ghost_r[v];
-        }
-    }
-    bool in[P];
-#pragma unroll
-    for (int k = 0; k < P; ++k) {
-        // la, lb take two values each over k: four distinct lane compares per level
-        int la, lb;
-        element_lane_bounds(P, R, INC, SMOD, lo, hi, base, k, la, lb);
-        in[k] = lane >= la && lane < lb;
-    }
-    Sch::template level<P, MULTI || Sch::SELECT_ONE_WAVE>(dst, ext, ODD, a.c, in);
-}
-
-// Levels s0 + U, s0 + U + 1, ... of one aligned group (s0 = 1 mod G, so the
-// row parity and the residues of the computed set are compile-time).  m = s for
-// a widening segment, m = mtop - s for a narrowing one.
-template <class Sch, int P, bool MULTI, bool WALL, bool INC, int U, int G>
-__device__ __forceinline__ void run_group(const TileArgs &a, int g, int NW, int s0, int s_last, int mtop,
-                                          bool full, double (&r0)[Sch::NV][P], double (&r1)[Sch::NV][P],
-                                          const double (&hl)[Sch::NV][Sch::R],
-                                          const double (&hr)[Sch::NV][Sch::R],
-                                          double (*xch)[16][2][Sch::NV][Sch::R])
-{
-    if constexpr (U < G) {
-        const int s = s0 + U;
-        if (full || s <= s_last) {
-            const int m = INC ? s : mtop - s;
-            constexpr int SMOD = (1 + U) % G;
-            if constexpr (((1 + U) & 1) != 0)
-                level_step<Sch, P, true, MULTI, WALL, INC, SMOD>(a, g, NW, s, m, r0, r1, hl, hr, xch);
-            else
-                level_step<Sch, P, false, MULTI, WALL, INC, SMOD>(a, g, NW, s, m, r1, r0, hl, hr, xch);
-            run_group<Sch, P, MULTI, WALL, INC, U + 1, G>(a, g, NW, s0, s_last, mtop, full, r0, r1, hl, hr, xch);
-        }
-    }
-}
-
-// Levels [s_first, s_last] (s_first = 1 mod G) in full groups plus one partial group.
-template <class Sch, int P, bool MULTI, bool WALL, bool INC>
-__device__ __forceinline__ void run_segment(const TileArgs &a, int g, int NW, int s_first, int s_last,
-                                            int mtop, double (&r0)[Sch::NV][P], double (&r1)[Sch::NV][P],
-                                            const double (&hl)[Sch::NV][Sch::R],
-                                            const double (&hr)[Sch::NV][Sch::R],
-                                            double (*xch)[16][2][Sch::NV][Sch::R])
-{
-    constexpr int G = group_len(P, Sch::R);
-    int s0 = s_first;
-    for (; s0 + G - 1 <= s_last; s0 += G)
-        run_group<Sch, P, MULTI, WALL, INC, 0, G>(a, g, NW, s0, s_last, mtop, true, r0, r1, hl, hr, xch);
-    if (s0 <= s_last)
-        run_group<Sch, P, MULTI, WALL, INC, 0, G>(a, g, NW, s0, s_last, mtop, false, r0, r1, hl, hr, xch);
-}
-
-template <class Sch, int P, bool MULTI, bool WALL>
-__device__ __forceinline__ void run_levels(const TileArgs &a, int g, int NW, double (&r0)[Sch::NV][P],
-                                           double (&r1)[Sch::NV][P], const double (&hl)[Sch::NV][Sch::R],
-                                           const double (&hr)[Sch::NV][Sch::R],
-                                           double (*xch)[16][2][Sch::NV][Sch::R])
-{
-    const int nlev = tile_levels(a);
-    if (a.kind == PH_UP) {
-        run_segment<Sch, P, MULTI, WALL, false>(a, g, NW, 1, nlev, a.H, r0, r1, hl, hr, xch);
-    } else if (a.kind == PH_DOWN) {
-        run_segment<Sch, P, MULTI, WALL, true>(a, g, NW, 1, nlev, 0, r0, r1, hl, hr, xch);
-    } else {
-        run_segment<Sch, P, MULTI, WALL, true>(a, g, NW, 1, a.H, 0, r0, r1, hl, hr, xch);
-        run_segment<Sch, P, MULTI, WALL, false>(a, g, NW, a.H + 1, nlev, 2 * a.H, r0, r1, hl, hr, xch);
-    }
-}
-
-// One tile of one phase: load the two rows, run the phase's levels, store.
-template <class Sch, int P>
-__device__ __forceinline__ void tile_body(const TileArgs &args, int64_t j, int g, int NW,
-                                          double (*xch)[16][2][Sch::NV][Sch::R])
-{
-    constexpr int NV = Sch::NV, R = Sch::R;
-    TileArgs a = args;
-    a.ends = tile_ends(args, j);
-    double r0[NV][P], r1[NV][P], hl[NV][R], hr[NV][R];
-    lane_load<Sch, P>(a, j, g, r0, r1, hl, hr);
-    const bool wall = straddles_wall(a, j);
-    if (NW > 1) {
-        if (wall) run_levels<Sch, P, true, true>(a, g, NW, r0, r1, hl, hr, xch);
-        else run_levels<Sch, P, true, false>(a, g, NW, r0, r1, hl, hr, xch);
-        __syncthreads();  // every wave has read its inputs before any slot is rewritten
-    } else {
-        if (wall) run_levels<Sch, P, false, true>(a, g, NW, r0, r1, hl, hr, xch);
-        else run_levels<Sch, P, false, false>(a, g, NW, r0, r1, hl, hr, xch);
-    }
-    lane_store<Sch, P>(a, j, g, r0, r1);
-}
-
-template <class Sch, int P, int MAXT>
-__global__ __launch_bounds__(MAXT) void swept_tile(TileArgs a)
-{
-    __shared__ double xch[2][16][2][Sch::NV][Sch::R];
-    tile_body<Sch, P>(a, (int64_t)blockIdx.x, (int)threadIdx.x, (int)(blockDim.x >> 6), xch);
-}
-
-// Batched phase: every work item is (solve, tile) of one of many independent
-// solves; one-wave work-groups stride over the items, so a launch covers the
-// current phase of every solve in the batch.  `global_phase` >= 0 runs that
-// phase for every solve; -1 takes each solve's own phase (served batches).
-template <class Sch, int P>
-__global__ __launch_bounds__(64) void batch_tiles(const SolveDesc *__restrict__ desc,
-                                                  const int2 *__restrict__ items, int64_t nitems,
-                                                  int global_phase)
-{
-    __shared__ double xch[2][16][2][Sch::NV][Sch::R];
-    for (int64_t i = blockIdx.x; i < nitems; i += gridDim.x) {
-        const int2 it = items[i];
-        const SolveDesc &d = desc[it.x];
-        const int p = global_phase >= 0 ? global_phase : d.phase;
-        if (p >= d.nphases) continue;
-        TileArgs a;
-        a.state = d.state;
-        a.edges = d.edges;
-        a.n = d.n;
-        a.K = d.K;
-        a.w = d.w;
-        a.H = d.H;
-        a.E = d.E;
-        a.bc = d.bc;
-        a.ends = 0;
-        a.c = d.c;
-        phase_at(d.Q, d.rem, d.H, p, a.kind, a.levels, a.offset);
-        tile_body<Sch, P>(a, (int64_t)it.y, (int)threadIdx.x, 1, xch);
-    }
-}
 
 // Classic: one thread per point, one launch per sub-step (Sec. 4.1).  For the
 // final RK2 stage `dst` holds u^m and is updated in place (the listing's +=).
@@ -353,37 +67,14 @@ __global__ void nonfinite_scan(const double *x, int64_t count, int *flag)
         if (!isfinite(x[i])) atomicOr(flag, 1);
 }
 
-template <class Sch, int P>
-hipError_t launch_tile(const TileArgs &a, int threads, hipStream_t st)
-{
-    constexpr int MAXT = max_threads_for(Sch::NV, P);
-    if (threads > MAXT) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((swept_tile<Sch, P, MAXT>), dim3((unsigned)a.K), dim3(threads), 0, st, a);
-    return hipGetLastError();
-}
-
-template <class Sch>
-hipError_t launch_tile_p(const TileArgs &a, int P, int threads, hipStream_t st)
-{
-    switch (P) {
-    case 1: return launch_tile<Sch, 1>(a, threads, st);
-    case 2: return launch_tile<Sch, 2>(a, threads, st);
-    case 4: return launch_tile<Sch, 4>(a, threads, st);
-    case 8: return launch_tile<Sch, 8>(a, threads, st);
-    case 16: if constexpr (Sch::NV == 1) return launch_tile<Sch, 16>(a, threads, st); break;
-    default: break;
-    }
-    return hipErrorInvalidValue;
-}
-
 }  // namespace
 
 hipError_t launch_swept_phase(int scheme, int P, int threads, const TileArgs &a, hipStream_t st)
 {
     if (a.K <= 0) return hipSuccess;
-    if (scheme == 0) return launch_tile_p<Heat>(a, P, threads, st);
-    if (scheme == 1) return launch_tile_p<KS>(a, P, threads, st);
-    return launch_tile_p<Euler>(a, P, threads, st);
+    if (scheme == 0) return swept_phase_for<Heat>(P, threads, a, st);
+    if (scheme == 1) return swept_phase_for<KS>(P, threads, a, st);
+    return swept_phase_for<Euler>(P, threads, a, st);
 }
 
 hipError_t launch_classic_level(int scheme, const double *src, double *dst, int64_t n, int bc,
@@ -400,69 +91,20 @@ hipError_t launch_classic_level(int scheme, const double *src, double *dst, int6
     return hipGetLastError();
 }
 
-namespace {
-
-template <class Sch, int P>
-hipError_t batch_launch_t(const SolveDesc *desc, const int2 *items, int64_t nitems, int global_phase,
-                          int grid, hipStream_t st)
-{
-    hipLaunchKernelGGL((batch_tiles<Sch, P>), dim3((unsigned)grid), dim3(64), 0, st, desc, items, nitems,
-                       global_phase);
-    return hipGetLastError();
-}
-
-template <class Sch, int P>
-int batch_occupancy_t()
-{
-    int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_tiles<Sch, P>, 64, 0) != hipSuccess) {
-        (void)hipGetLastError();
-        return 1;
-    }
-    return n > 0 ? n : 1;
-}
-
-template <class Sch>
-hipError_t batch_launch_s(int P, const SolveDesc *desc, const int2 *items, int64_t nitems, int global_phase,
-                          int grid, hipStream_t st)
-{
-    switch (P) {
-    case 1: return batch_launch_t<Sch, 1>(desc, items, nitems, global_phase, grid, st);
-    case 2: return batch_launch_t<Sch, 2>(desc, items, nitems, global_phase, grid, st);
-    case 4: return batch_launch_t<Sch, 4>(desc, items, nitems, global_phase, grid, st);
-    case 8: return batch_launch_t<Sch, 8>(desc, items, nitems, global_phase, grid, st);
-    default: return hipErrorInvalidValue;
-    }
-}
-
-template <class Sch>
-int batch_occupancy_s(int P)
-{
-    switch (P) {
-    case 1: return batch_occupancy_t<Sch, 1>();
-    case 2: return batch_occupancy_t<Sch, 2>();
-    case 4: return batch_occupancy_t<Sch, 4>();
-    case 8: return batch_occupancy_t<Sch, 8>();
-    default: return 1;
-    }
-}
-
-}  // namespace
-
 hipError_t launch_batch_phase(int scheme, int P, const SolveDesc *desc, const int2 *items, int64_t nitems,
                               int global_phase, int grid, hipStream_t st)
 {
     if (nitems <= 0) return hipSuccess;
-    if (scheme == 0) return batch_launch_s<Heat>(P, desc, items, nitems, global_phase, grid, st);
-    if (scheme == 1) return batch_launch_s<KS>(P, desc, items, nitems, global_phase, grid, st);
-    return batch_launch_s<Euler>(P, desc, items, nitems, global_phase, grid, st);
+    if (scheme == 0) return batch_phase_for<Heat>(P, desc, items, nitems, global_phase, grid, st);
+    if (scheme == 1) return batch_phase_for<KS>(P, desc, items, nitems, global_phase, grid, st);
+    return batch_phase_for<Euler>(P, desc, items, nitems, global_phase, grid, st);
 }
 
 int batch_blocks_per_cu(int scheme, int P)
 {
-    if (scheme == 0) return batch_occupancy_s<Heat>(P);
-    if (scheme == 1) return batch_occupancy_s<KS>(P);
-    return batch_occupancy_s<Euler>(P);
+    if (scheme == 0) return batch_blocks_for<Heat>(P);
+    if (scheme == 1) return batch_blocks_for<KS>(P);
+    return batch_blocks_for<Euler>(P);
 }
 
 hipError_t launch_advance_phases(SolveDesc *desc, int64_t n, hipStream_t st)

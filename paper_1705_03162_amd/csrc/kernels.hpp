@@ -1,4 +1,4 @@
-// Launchers of the HIP kernels in kernels.hip (host-callable).
+// Launchers of the HIP kernels in kernels.hip and swept_tile.hpp (host-callable).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -19,6 +19,17 @@ hipError_t launch_classic_level(int scheme, const double *src, double *dst, int6
 // `grid` one-wave work-groups stride over the items.
 hipError_t launch_batch_phase(int scheme, int P, const SolveDesc *desc, const int2 *items, int64_t nitems,
                               int global_phase, int grid, hipStream_t st);
+
+// Per-scheme launchers of the swept tile kernels, defined in swept_tile.hpp and
+// instantiated for Heat, KS and Euler in tiles_heat.hip, tiles_ks.hip and
+// tiles_euler.hip (the dispatch above calls them).
+template <class Sch>
+hipError_t swept_phase_for(int P, int threads, const TileArgs &a, hipStream_t st);
+template <class Sch>
+hipError_t batch_phase_for(int P, const SolveDesc *desc, const int2 *items, int64_t nitems, int global_phase,
+                           int grid, hipStream_t st);
+template <class Sch>
+int batch_blocks_for(int P);
 
 // desc[i].phase += 1 for every solve i < n that has phases left (served ticks).
 hipError_t launch_advance_phases(SolveDesc *desc, int64_t n, hipStream_t st);

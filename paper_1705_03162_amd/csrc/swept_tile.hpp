@@ -1,0 +1,438 @@
+// Device code of the swept tile kernel (Up / Diamond / Down phases) and of its
+// batched form, with their per-scheme launchers.  Each scheme's kernels are
+// instantiated in a translation unit of their own (tiles_heat.hip,
+// tiles_ks.hip, tiles_euler.hip), which keeps the unrolled level loops of the
+// three schemes compiling in parallel.
+//
+// One work-group is one node of the swept rule (the paper's Shared variant maps
+// a node to a block, Sec. 4.1), but the two-row working array lives in VGPRs
+// instead of shared memory: lane g owns P consecutive points of both rows.  Per
+// level a lane needs r points of the source row from each neighbouring lane;
+// inside a wave they arrive through DPP row moves across the whole wave
+// (wave_shr:1 / wave_shl:1), between waves through a small double-buffered LDS
+// exchange with one barrier per level.  A one-wave tile therefore runs
+// barrier-free.  A stencil update is no matrix product, so MFMA has no role; the
+// kernel is bound by FP64 VALU issue (fused multiply-adds where the canonical
+// rules write them, nothing contracted implicitly).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "kernels.hpp"
+
+namespace sw {
+
+namespace {
+
+constexpr int DPP_WAVE_SHL1 = 0x130;  // lane i receives lane i+1
+constexpr int DPP_WAVE_SHR1 = 0x138;  // lane i receives lane i-1
+
+// Zero-filling DPP move: lanes whose source lies outside the wave read 0.
+template <int CTRL>
+__device__ __forceinline__ double dpp_zero(double v)
+{
+    const unsigned long long x = __builtin_bit_cast(unsigned long long, v);
+    const int lo = __builtin_amdgcn_mov_dpp((int)(unsigned)x, CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(unsigned)(x >> 32), CTRL, 0xF, 0xF, true);
+    const unsigned long long r = ((unsigned long long)(unsigned)hi << 32) | (unsigned long long)(unsigned)lo;
+    return __builtin_bit_cast(double, r);
+}
+
+// One level of a tile: gather the source row with halos, then update the points
+// of the computed set [w/2 - r m, w/2 + r m).  Element k of the wave's lanes is
+// inside for a contiguous range of lanes whose ends take only two values each
+// over k (their residues are compile-time), so a level needs four lane compares
+// however many points a lane holds.  A wave with no point inside skips the level
+// (after publishing its boundary values for its neighbours), which recovers most
+// of the idle half of a triangle in multi-wave tiles.
+template <class Sch, int P, bool ODD, bool MULTI, bool WALL, bool INC, int SMOD>
+__device__ __forceinline__ void level_step(const TileArgs &a, int g, int NW, int s, int m,
+                                           const double (&src)[Sch::NV][P], double (&dst)[Sch::NV][P],
+                                           const double (&hl)[Sch::NV][Sch::R],
+                                           const double (&hr)[Sch::NV][Sch::R],
+                                           double (*xch)[16][2][Sch::NV][Sch::R])
+{
+    constexpr int NV = Sch::NV, R = Sch::R;
+    const int lane = g & 63, wave = g >> 6, buf = s & 1;
+    if (MULTI) {
+        // publish this wave's first and last R points (wave positions p = lane P + k)
+        if (lane * P < R) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v)
+#pragma unroll
+                for (int k = 0; k < P; ++k)
+                    if (lane * P + k < R) xch[buf][wave][0][v][lane * P + k] = src[v][k];
+        }
+        if (lane * P + P > 64 * P - R) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v)
+#pragma unroll
+                for (int k = 0; k < P; ++k)
+                    if (lane * P + k >= 64 * P - R) xch[buf][wave][1][v][lane * P + k - (64 * P - R)] = src[v][k];
+        }
+        __syncthreads();
+    }
+    const int half = a.w >> 1;
+    const int lo = __builtin_amdgcn_readfirstlane(half - R * m);
+    const int hi = __builtin_amdgcn_readfirstlane(half + R * m);
+    // first lane of this wave (a one-wave tile is lane 0 onwards)
+    const int base = MULTI ? __builtin_amdgcn_readfirstlane(g & ~63) : 0;
+    if (MULTI) {
+        // lanes of this wave holding at least one computed point: [lmin, lmax); a
+        // one-wave tile always holds some (the computed set is never empty)
+        int lmin, lmax;
+        element_lane_span(P, R, INC, SMOD, lo, hi, base, lmin, lmax);
+        if (!(lmin < 64 && lmax > 0 && lmin < lmax)) return;
+    }
+
+    // ext[v][i] holds tile position g P - R + i, ext[v][R + P + i] position g P + P + i.
+    static_assert(P >= R || P == 1, "a lane's halo spans at most its neighbours, or one point per lane");
+    double ext[NV][P + 2 * R];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+#pragma unroll
+        for (int k = 0; k < P; ++k) ext[v][R + k] = src[v][k];
+        if constexpr (P >= R) {
+#pragma unroll
+            for (int i = 0; i < R; ++i) {
+                ext[v][i] = dpp_zero<DPP_WAVE_SHR1>(src[v][P - R + i]);
+                ext[v][R + P + i] = dpp_zero<DPP_WAVE_SHL1>(src[v][i]);
+            }
+        } else {  // one point per lane: points further away pass through successive lanes
+            ext[v][R - 1] = dpp_zero<DPP_WAVE_SHR1>(src[v][0]);
+#pragma unroll
+            for (int i = R - 2; i >= 0; --i) ext[v][i] = dpp_zero<DPP_WAVE_SHR1>(ext[v][i + 1]);
+            ext[v][R + 1] = dpp_zero<DPP_WAVE_SHL1>(src[v][0]);
+#pragma unroll
+            for (int i = 1; i < R; ++i) ext[v][R + 1 + i] = dpp_zero<DPP_WAVE_SHL1>(ext[v][R + i]);
+        }
+    }
+    const int x0 = g * P;  // first tile position of this lane
+    // The tile's outer halo is read by the widest level of a Diamond/Down only.
+    if (s == a.H && a.kind != PH_UP) {
+        const bool refl = a.bc == BC_REFLECTIVE;  // heat only: R == 1
+        if (x0 < R) {
+            if (refl && (a.ends & 1)) {
+                if constexpr (R == 1)
+                    if (x0 == 0) ext[0][0] = ext[0][mirror_left_src(R, 0)];
+            } else {
+#pragma unroll
+                for (int v = 0; v < NV; ++v)
+#pragma unroll
+                    for (int i = 0; i < R; ++i)
+                        if (x0 - R + i < 0) ext[v][i] = hl[v][x0 + i];
+            }
+        }
+        if (x0 + P + R > a.w) {
+            if (refl && (a.ends & 2)) {
+                if constexpr (R == 1)
+                    if (x0 + P == a.w) ext[0][R + P] = ext[0][mirror_right_src(P, R, 0)];
+            } else {
+#pragma unroll
+                for (int v = 0; v < NV; ++v)
+#pragma unroll
+                    for (int i = 0; i < R; ++i)
+                        if (x0 + P + i >= a.w) ext[v][R + P + i] = hr[v][x0 + P + i - a.w];
+            }
+        }
+    }
+    if (MULTI) {
+        if (lane * P < R && wave > 0) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v)
+#pragma unroll
+                for (int i = 0; i < R; ++i)
+                    if (lane * P - R + i < 0) ext[v][i] = xch[buf][wave - 1][1][v][lane * P + i];
+        }
+        if (lane * P + P + R > 64 * P && wave < NW - 1) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v)
+#pragma unroll
+                for (int i = 0; i < R; ++i)
+                    if (lane * P + P + i >= 64 * P)
+                        ext[v][R + P + i] = xch[buf][wave + 1][0][v][lane * P + P + i - 64 * P];
+        }
+    }
+    if (WALL && a.bc == BC_REFLECTIVE) {  // insulated ends meet at the tile centre (heat, R == 1)
+        if constexpr (R == 1) {
+            if (x0 == half) ext[0][0] = ext[0][mirror_left_src(R, 0)];
+            if (x0 + P == half) ext[0][R + P] = ext[0][mirror_right_src(P, R, 0)];
+        }
+    } else if (WALL) {  // Dirichlet wall at the tile centre: across it lie the ghost values
+        if (x0 >= half && x0 - R < half) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v)
+#pragma unroll
+                for (int i = 0; i < R; ++i)
+                    if (x0 - R + i < half) ext[v][i] = a.c.ghost_l[v];
+        }
+        if (x0 < half && x0 + P + R > half) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v)
+#pragma unroll
+                for (int i = 0; i < R; ++i)
+                    if (x0 + P + i >= half) ext[v][R + P + i] = a.c.ghost_r[v];
+        }
+    }
+    bool in[P];
+#pragma unroll
+    for (int k = 0; k < P; ++k) {
+        // la, lb take two values each over k: four distinct lane compares per level
+        int la, lb;
+        element_lane_bounds(P, R, INC, SMOD, lo, hi, base, k, la, lb);
+        in[k] = lane >= la && lane < lb;
+    }
+    Sch::template level<P, MULTI || Sch::SELECT_ONE_WAVE>(dst, ext, ODD, a.c, in);
+}
+
+// Levels s0 + U, s0 + U + 1, ... of one aligned group (s0 = 1 mod G, so the
+// row parity and the residues of the computed set are compile-time).  m = s for
+// a widening segment, m = mtop - s for a narrowing one.
+template <class Sch, int P, bool MULTI, bool WALL, bool INC, int U, int G>
+__device__ __forceinline__ void run_group(const TileArgs &a, int g, int NW, int s0, int s_last, int mtop,
+                                          bool full, double (&r0)[Sch::NV][P], double (&r1)[Sch::NV][P],
+                                          const double (&hl)[Sch::NV][Sch::R],
+                                          const double (&hr)[Sch::NV][Sch::R],
+                                          double (*xch)[16][2][Sch::NV][Sch::R])
+{
+    if constexpr (U < G) {
+        const int s = s0 + U;
+        if (full || s <= s_last) {
+            const int m = INC ? s : mtop - s;
+            constexpr int SMOD = (1 + U) % G;
+            if constexpr (((1 + U) & 1) != 0)
+                level_step<Sch, P, true, MULTI, WALL, INC, SMOD>(a, g, NW, s, m, r0, r1, hl, hr, xch);
+            else
+                level_step<Sch, P, false, MULTI, WALL, INC, SMOD>(a, g, NW, s, m, r1, r0, hl, hr, xch);
+            run_group<Sch, P, MULTI, WALL, INC, U + 1, G>(a, g, NW, s0, s_last, mtop, full, r0, r1, hl, hr, xch);
+        }
+    }
+}
+
+// Levels [s_first, s_last] (s_first = 1 mod G) in full groups plus one partial group.
+template <class Sch, int P, bool MULTI, bool WALL, bool INC>
+__device__ __forceinline__ void run_segment(const TileArgs &a, int g, int NW, int s_first, int s_last,
+                                            int mtop, double (&r0)[Sch::NV][P], double (&r1)[Sch::NV][P],
+                                            const double (&hl)[Sch::NV][Sch::R],
+                                            const double (&hr)[Sch::NV][Sch::R],
+                                            double (*xch)[16][2][Sch::NV][Sch::R])
+{
+    constexpr int G = group_len(P, Sch::R);
+    int s0 = s_first;
+    for (; s0 + G - 1 <= s_last; s0 += G)
+        run_group<Sch, P, MULTI, WALL, INC, 0, G>(a, g, NW, s0, s_last, mtop, true, r0, r1, hl, hr, xch);
+    if (s0 <= s_last)
+        run_group<Sch, P, MULTI, WALL, INC, 0, G>(a, g, NW, s0, s_last, mtop, false, r0, r1, hl, hr, xch);
+}
+
+template <class Sch, int P, bool MULTI, bool WALL>
+__device__ __forceinline__ void run_levels(const TileArgs &a, int g, int NW, double (&r0)[Sch::NV][P],
+                                           double (&r1)[Sch::NV][P], const double (&hl)[Sch::NV][Sch::R],
+                                           const double (&hr)[Sch::NV][Sch::R],
+                                           double (*xch)[16][2][Sch::NV][Sch::R])
+{
+    const int nlev = tile_levels(a);
+    if (a.kind == PH_UP) {
+        run_segment<Sch, P, MULTI, WALL, false>(a, g, NW, 1, nlev, a.H, r0, r1, hl, hr, xch);
+    } else if (a.kind == PH_DOWN) {
+        run_segment<Sch, P, MULTI, WALL, true>(a, g, NW, 1, nlev, 0, r0, r1, hl, hr, xch);
+    } else {
+        run_segment<Sch, P, MULTI, WALL, true>(a, g, NW, 1, a.H, 0, r0, r1, hl, hr, xch);
+        run_segment<Sch, P, MULTI, WALL, false>(a, g, NW, a.H + 1, nlev, 2 * a.H, r0, r1, hl, hr, xch);
+    }
+}
+
+// One-wave tiles store their rows through LDS.  A lane holds P consecutive
+// points, so a direct store writes one double per lane at a stride of P doubles
+// and a 128-byte line fills only over P store instructions (partly written lines
+// then leave the L2 more than once); staged point-major, consecutive lanes store
+// consecutive positions and every store instruction writes whole lines.  One
+// padding double per P points keeps both LDS passes free of bank conflicts.
+template <int P>
+constexpr int stage_span() { return 64 * P + 64; }
+
+template <class Sch, int P>
+__device__ __forceinline__ void wave_store(const TileArgs &a, int64_t j, int lane, const double (&r0)[Sch::NV][P],
+                                           const double (&r1)[Sch::NV][P], double *stage)
+{
+    constexpr int NV = Sch::NV, SPAN = stage_span<P>();
+    __syncthreads();  // the work-group's previous tile has finished reading the stage
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            stage[(2 * v + 0) * SPAN + lane * (P + 1) + k] = r0[v][k];
+            stage[(2 * v + 1) * SPAN + lane * (P + 1) + k] = r1[v][k];
+        }
+    __syncthreads();
+    if (a.kind != PH_DOWN) {
+        double *sa = a.edges + slot_base<Sch>(a, slot_a(a, j));
+        double *sb = a.edges + slot_base<Sch>(a, slot_b(a, j));
+#pragma unroll
+        for (int i = 0; i < P; ++i) {
+            const int x = 64 * i + lane, idx = x + x / P;
+#pragma unroll
+            for (int v = 0; v < NV; ++v)
+                store_edge_point<Sch>(a, sa, sb, v, x, stage[(2 * v + 0) * SPAN + idx],
+                                      stage[(2 * v + 1) * SPAN + idx]);
+        }
+    }
+    int lo, hi;
+    const int top = store_top_level<Sch>(a, lo, hi);
+    if (top < 0) return;
+    const int64_t g0 = tile_start(a, j);
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+        const int x = 64 * i + lane, idx = x + x / P;
+        if (x >= lo && x < hi) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v)
+                store_top_point<Sch>(a, g0, top, v, x, stage[(2 * v + 0) * SPAN + idx],
+                                     stage[(2 * v + 1) * SPAN + idx]);
+        }
+    }
+}
+
+// One tile of one phase: load the two rows, run the phase's levels, store.
+// `stage` (one-wave work-groups only) holds 2 NV stage_span<P>() doubles of LDS.
+template <class Sch, int P>
+__device__ __forceinline__ void tile_body(const TileArgs &args, int64_t j, int g, int NW,
+                                          double (*xch)[16][2][Sch::NV][Sch::R], double *stage)
+{
+    constexpr int NV = Sch::NV, R = Sch::R;
+    TileArgs a = args;
+    a.ends = tile_ends(args, j);
+    double r0[NV][P], r1[NV][P], hl[NV][R], hr[NV][R];
+    lane_load<Sch, P>(a, j, g, r0, r1, hl, hr);
+    const bool wall = straddles_wall(a, j);
+    if (NW > 1) {
+        if (wall) run_levels<Sch, P, true, true>(a, g, NW, r0, r1, hl, hr, xch);
+        else run_levels<Sch, P, true, false>(a, g, NW, r0, r1, hl, hr, xch);
+        __syncthreads();  // every wave has read its inputs before any slot is rewritten
+    } else {
+        if (wall) run_levels<Sch, P, false, true>(a, g, NW, r0, r1, hl, hr, xch);
+        else run_levels<Sch, P, false, false>(a, g, NW, r0, r1, hl, hr, xch);
+    }
+    if (stage) wave_store<Sch, P>(a, j, g, r0, r1, stage);
+    else lane_store<Sch, P>(a, j, g, r0, r1);
+}
+
+// MAXT bounds the work-group size the kernel is compiled for.  MAXT = 64 is the
+// one-wave tile: the multi-wave path (LDS exchange, barriers) is compiled out,
+// the rows are stored through LDS, and the register allocator is not held to the
+// 1024-lane bound's share of the file.
+template <class Sch, int P, int MAXT>
+__global__ __launch_bounds__(MAXT) void swept_tile(TileArgs a)
+{
+    __shared__ double xch[2][16][2][Sch::NV][Sch::R];
+    __shared__ double stage[MAXT == 64 ? 2 * Sch::NV * stage_span<P>() : 1];
+    const int NW = MAXT == 64 ? 1 : (int)(blockDim.x >> 6);
+    tile_body<Sch, P>(a, (int64_t)blockIdx.x, (int)threadIdx.x, NW, xch, MAXT == 64 ? stage : nullptr);
+}
+
+// Batched phase: every work item is (solve, tile) of one of many independent
+// solves; one-wave work-groups stride over the items, so a launch covers the
+// current phase of every solve in the batch.  `global_phase` >= 0 runs that
+// phase for every solve; -1 takes each solve's own phase (served batches).
+template <class Sch, int P>
+__global__ __launch_bounds__(64) void batch_tiles(const SolveDesc *__restrict__ desc,
+                                                  const int2 *__restrict__ items, int64_t nitems,
+                                                  int global_phase)
+{
+    __shared__ double xch[2][16][2][Sch::NV][Sch::R];
+    __shared__ double stage[2 * Sch::NV * stage_span<P>()];
+    for (int64_t i = blockIdx.x; i < nitems; i += gridDim.x) {
+        const int2 it = items[i];
+        const SolveDesc &d = desc[it.x];
+        const int p = global_phase >= 0 ? global_phase : d.phase;
+        if (p >= d.nphases) continue;
+        TileArgs a;
+        a.state = d.state;
+        a.edges = d.edges;
+        a.n = d.n;
+        a.K = d.K;
+        a.w = d.w;
+        a.H = d.H;
+        a.E = d.E;
+        a.bc = d.bc;
+        a.ends = 0;
+        a.c = d.c;
+        phase_at(d.Q, d.rem, d.H, p, a.kind, a.levels, a.offset);
+        tile_body<Sch, P>(a, (int64_t)it.y, (int)threadIdx.x, 1, xch, stage);
+    }
+}
+
+template <class Sch, int P>
+hipError_t launch_tile(const TileArgs &a, int threads, hipStream_t st)
+{
+    constexpr int MAXT = max_threads_for(Sch::NV, P);
+    if (threads > MAXT) return hipErrorInvalidValue;
+    if (threads == 64)
+        hipLaunchKernelGGL((swept_tile<Sch, P, 64>), dim3((unsigned)a.K), dim3(64), 0, st, a);
+    else
+        hipLaunchKernelGGL((swept_tile<Sch, P, MAXT>), dim3((unsigned)a.K), dim3(threads), 0, st, a);
+    return hipGetLastError();
+}
+
+template <class Sch, int P>
+hipError_t batch_launch_t(const SolveDesc *desc, const int2 *items, int64_t nitems, int global_phase,
+                          int grid, hipStream_t st)
+{
+    hipLaunchKernelGGL((batch_tiles<Sch, P>), dim3((unsigned)grid), dim3(64), 0, st, desc, items, nitems,
+                       global_phase);
+    return hipGetLastError();
+}
+
+template <class Sch, int P>
+int batch_occupancy_t()
+{
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_tiles<Sch, P>, 64, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        return 1;
+    }
+    return n > 0 ? n : 1;
+}
+
+}  // namespace
+
+template <class Sch>
+hipError_t swept_phase_for(int P, int threads, const TileArgs &a, hipStream_t st)
+{
+    switch (P) {
+    case 1: return launch_tile<Sch, 1>(a, threads, st);
+    case 2: return launch_tile<Sch, 2>(a, threads, st);
+    case 4: return launch_tile<Sch, 4>(a, threads, st);
+    case 8: return launch_tile<Sch, 8>(a, threads, st);
+    case 16: if constexpr (Sch::NV == 1) return launch_tile<Sch, 16>(a, threads, st); break;
+    default: break;
+    }
+    return hipErrorInvalidValue;
+}
+
+template <class Sch>
+hipError_t batch_phase_for(int P, const SolveDesc *desc, const int2 *items, int64_t nitems, int global_phase,
+                           int grid, hipStream_t st)
+{
+    switch (P) {
+    case 1: return batch_launch_t<Sch, 1>(desc, items, nitems, global_phase, grid, st);
+    case 2: return batch_launch_t<Sch, 2>(desc, items, nitems, global_phase, grid, st);
+    case 4: return batch_launch_t<Sch, 4>(desc, items, nitems, global_phase, grid, st);
+    case 8: return batch_launch_t<Sch, 8>(desc, items, nitems, global_phase, grid, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <class Sch>
+int batch_blocks_for(int P)
+{
+    switch (P) {
+    case 1: return batch_occupancy_t<Sch, 1>();
+    case 2: return batch_occupancy_t<Sch, 2>();
+    case 4: return batch_occupancy_t<Sch, 4>();
+    case 8: return batch_occupancy_t<Sch, 8>();
+    default: return 1;
+    }
+}
+
+}  // namespace sw

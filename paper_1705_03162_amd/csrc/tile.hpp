@@ -38,7 +38,7 @@ enum BcKind : int32_t { BC_PERIODIC = 0, BC_DIRICHLET = 1, BC_REFLECTIVE = 2 };
 
 // Largest work-group for which a tile kernel is compiled: the two rows take
 // 2*nv*P doubles per lane, and the register file must hold them for every wave.
-constexpr int max_threads_for(int nv, int P) { return nv > 1 ? (P >= 8 ? 256 : 512) : (P >= 16 ? 512 : 1024); }
+constexpr int max_threads_for(int nv, int P) { return nv > 1 ? (P >= 8 ? 256 : 512) : (P >= 8 ? 512 : 1024); }
 
 struct TileArgs {
     double *state;     // [nv][n]
@@ -202,53 +202,71 @@ SW_HD void lane_load(const TileArgs &a, int64_t j, int g, double (&r0)[Sch::NV][
     }
 }
 
-// Store lane g's rows: Up and Diamond write the new L slot (into a) and R slot
-// (into b); an Up that stops below the triangle tip, and every Down, also write
-// their top level's computed points to the state.
+// Where a tile's final rows go.  Up and Diamond write the new L slot (into a:
+// positions x < w/2 + r) and R slot (into b: x >= w/2 - r) of both rows; an Up
+// that stops below the triangle tip, and every Down, also write their top
+// level's computed points [lo, hi) to the state.
+template <class Sch>
+SW_HD void store_edge_point(const TileArgs &a, double *sa, double *sb, int v, int x, double row0,
+                            double row1)
+{
+    constexpr int R = Sch::R;
+    const int half = a.w / 2;
+    if (x < half + R) {
+        sa[(v * 2 + 0) * a.E + x] = row0;
+        sa[(v * 2 + 1) * a.E + x] = row1;
+    }
+    if (x >= half - R) {
+        sb[(v * 2 + 0) * a.E + x - (half - R)] = row0;
+        sb[(v * 2 + 1) * a.E + x - (half - R)] = row1;
+    }
+}
+
+// Top level written to the state by this phase (-1: none) and its computed set.
+template <class Sch>
+SW_HD int store_top_level(const TileArgs &a, int &lo, int &hi)
+{
+    constexpr int R = Sch::R;
+    int top = -1;
+    if (a.kind == PH_DOWN) top = a.levels;
+    else if (a.kind == PH_UP && a.levels < a.H) top = a.levels;
+    const int m = a.kind == PH_DOWN ? top : a.H - top;
+    lo = a.w / 2 - R * m;
+    hi = a.w / 2 + R * m;
+    return top;
+}
+
+// Top-level value of tile position x written to the state (x in [lo, hi)).
+template <class Sch>
+SW_HD void store_top_point(const TileArgs &a, int64_t g0, int top, int v, int x, double row0, double row1)
+{
+    a.state[(int64_t)v * a.n + wrap_once(g0 + x, a.n)] = (top & 1) ? row1 : row0;
+}
+
+// Store lane g's rows (its P points at positions g P + k).
 template <class Sch, int P>
 SW_HD void lane_store(const TileArgs &a, int64_t j, int g, const double (&r0)[Sch::NV][P],
                       const double (&r1)[Sch::NV][P])
 {
-    constexpr int NV = Sch::NV, R = Sch::R;
-    const int half = a.w / 2;
+    constexpr int NV = Sch::NV;
     const int x0 = g * P;
     if (a.kind != PH_DOWN) {
         double *sa = a.edges + slot_base<Sch>(a, slot_a(a, j));
         double *sb = a.edges + slot_base<Sch>(a, slot_b(a, j));
 #pragma unroll
-        for (int v = 0; v < NV; ++v) {
+        for (int v = 0; v < NV; ++v)
 #pragma unroll
-            for (int k = 0; k < P; ++k) {
-                const int x = x0 + k;
-                if (x < half + R) {
-                    sa[(v * 2 + 0) * a.E + x] = r0[v][k];
-                    sa[(v * 2 + 1) * a.E + x] = r1[v][k];
-                }
-                if (x >= half - R) {
-                    sb[(v * 2 + 0) * a.E + x - (half - R)] = r0[v][k];
-                    sb[(v * 2 + 1) * a.E + x - (half - R)] = r1[v][k];
-                }
-            }
-        }
+            for (int k = 0; k < P; ++k) store_edge_point<Sch>(a, sa, sb, v, x0 + k, r0[v][k], r1[v][k]);
     }
-    int top = -1;
-    if (a.kind == PH_DOWN) top = a.levels;
-    else if (a.kind == PH_UP && a.levels < a.H) top = a.levels;
+    int lo, hi;
+    const int top = store_top_level<Sch>(a, lo, hi);
     if (top < 0) return;
-    const int m = a.kind == PH_DOWN ? top : a.H - top;
-    const int lo = half - R * m, hi = half + R * m;
     const int64_t g0 = tile_start(a, j);
 #pragma unroll
-    for (int v = 0; v < NV; ++v) {
+    for (int v = 0; v < NV; ++v)
 #pragma unroll
-        for (int k = 0; k < P; ++k) {
-            const int x = x0 + k;
-            if (x >= lo && x < hi) {
-                const double val = (top & 1) ? r1[v][k] : r0[v][k];
-                a.state[(int64_t)v * a.n + wrap_once(g0 + x, a.n)] = val;
-            }
-        }
-    }
+        for (int k = 0; k < P; ++k)
+            if (x0 + k >= lo && x0 + k < hi) store_top_point<Sch>(a, g0, top, v, x0 + k, r0[v][k], r1[v][k]);
 }
 
 // ---- per-element lane bounds with residues fixed by the level's position ----

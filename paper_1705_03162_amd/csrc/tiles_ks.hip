@@ -1,0 +1,11 @@
+// Swept tile kernels of the Kuramoto-Sivashinsky scheme: every points-per-lane variant of the
+// single-solve kernel (one-wave and multi-wave work-groups) and of the batched kernel.
+#include "swept_tile.hpp"
+
+namespace sw {
+
+template hipError_t swept_phase_for<KS>(int, int, const TileArgs &, hipStream_t);
+template hipError_t batch_phase_for<KS>(int, const SolveDesc *, const int2 *, int64_t, int, int, hipStream_t);
+template int batch_blocks_for<KS>(int);
+
+}  // namespace sw

@@ -26,7 +26,7 @@ WAVES = (1, 2, 4, 8, 16)
 def legal(scheme: int, P: int, threads: int) -> bool:
     if scheme == 2 and P > 8:
         return False
-    max_t = (256 if P >= 8 else 512) if scheme == 2 else (512 if P >= 16 else 1024)
+    max_t = (256 if P >= 8 else 512) if scheme == 2 else (512 if P >= 8 else 1024)
     return threads <= max_t
 
 

@@ -189,6 +189,20 @@ def test_invalid_shapes_rejected(lib, width, threads):
         assert rc == N.SW_EINVAL
 
 
+def test_eight_points_per_lane_caps_work_group_at_512(lib):
+    """With P >= 8 the rows take 2 P doubles per lane; the kernels are compiled for at
+    most 512 lanes (two waves per SIMD), so 16-wave tiles of 8 points per lane are refused."""
+    prob = W.ks_problem(1 << 14, 10)
+    rc, h = _plan(lib, prob, 4096, 512)
+    assert rc == 0
+    lib.swept_plan_destroy(h)
+    rc, _ = _plan(lib, prob, 8192, 1024)
+    assert rc == N.SW_EINVAL
+    rc, h = _plan(lib, prob, 1024, 1024)          # P = 1: 16 waves allowed
+    assert rc == 0
+    lib.swept_plan_destroy(h)
+
+
 def test_width_must_divide_n(lib):
     rc, _ = _plan(lib, W.heat_problem(1000, 10), 64, 64)
     assert rc == N.SW_EINVAL
