@@ -68,6 +68,16 @@ SMALL = [  # (problem factory, width, threads)
     (lambda: (W.heat_problem(4096, 1999, bc=W.REFLECTIVE), W.fourier_ic(4096, 14)), 1024, 256),
     (lambda: (W.heat_problem(2048, 700, bc=W.REFLECTIVE), W.fourier_ic(2048, 15)), 2048, 128),
     (lambda: (W.heat_problem(512, 333, bc=W.REFLECTIVE), W.fourier_ic(512, 16)), 128, 128),
+    # one-wave tiles of 16 points per lane (rows staged through LDS on load and store), with
+    # a remainder (Up that stops below its tip), Dirichlet and insulated walls
+    (lambda: (W.heat_problem(4096, 1777), W.fourier_ic(4096, 17)), 1024, 64),
+    (lambda: (W.heat_problem(3072, 1201, bc=W.DIRICHLET, bc_left=0.3, bc_right=-0.7),
+              W.fourier_ic(3072, 18)), 1024, 64),
+    (lambda: (W.heat_problem(2048, 1313, bc=W.REFLECTIVE), W.fourier_ic(2048, 19)), 1024, 64),
+    (lambda: (W.ks_problem(4096, 555), W.fourier_ic(4096, 20)), 1024, 64),
+    (lambda: (W.Problem(W.KS, 3072, 421, 2.0 ** -8, 0.5, bc=W.DIRICHLET, bc_left=(0.4, 0, 0),
+                        bc_right=(-0.2, 0, 0)), W.fourier_ic(3072, 21)), 1024, 64),
+    (lambda: (W.sod_problem(2048, 777), W.sod_ic(2048)), 512, 64),        # P = 8, three variables
 ]
 
 
@@ -260,7 +270,8 @@ def test_repeat_runs_bitwise_identical():
 
 def test_tile_shape_invariance_bitwise():
     prob, ic = W.cfg_sweep(W.KS, 14, nsteps=2000)
-    shapes = [(128, 64), (256, 64), (512, 64), (1024, 128), (2048, 256), (4096, 512), (1024, 512)]
+    shapes = [(128, 64), (256, 64), (512, 64), (1024, 64), (1024, 128), (2048, 128), (2048, 256),
+              (4096, 512), (1024, 512), (8192, 512)]
     outs = [gpu_solve(prob, ic, "swept", w, t) for w, t in shapes]
     assert all(np.array_equal(outs[0], o) for o in outs[1:])
 
