@@ -56,6 +56,7 @@ SW_HD double sw_fabs(double x) { return fabs(x); }
 struct Heat {
     static constexpr int R = 1, S = 1, NV = 1;
     static constexpr bool SELECT_ONE_WAVE = false;  // 4 operations per point: branch instead
+    static constexpr bool LANE_EXCHANGE = false;    // no per-cell quantity shared by neighbours
     template <int P, bool SEL = true>
     SW_HD static void level(double (&dst)[NV][P], const double (&ext)[NV][P + 2 * R],
                             bool /*predictor*/, const Consts &c, const bool (&in)[P])
@@ -77,6 +78,7 @@ struct Heat {
 struct KS {
     static constexpr int R = 2, S = 2, NV = 1;
     static constexpr bool SELECT_ONE_WAVE = true;
+    static constexpr bool LANE_EXCHANGE = false;
     // g_i(v) = -f_i(v) = (v_{i+1}^2 - v_{i-1}^2)/(4dx) + (v_{i+1} + v_{i-1} - 2v_i)/dx^2
     //                   + (v_{i+2} + v_{i-2} - 4(v_{i+1} + v_{i-1}) + 6v_i)/dx^4,
     // collected by symmetric stencil pair (s1 = v_{i+1} + v_{i-1}, d1 = v_{i+1} - v_{i-1},
@@ -112,6 +114,9 @@ struct KS {
 struct Euler {
     static constexpr int R = 2, S = 2, NV = 3;
     static constexpr bool SELECT_ONE_WAVE = true;
+    // Pressures, pressure ratios and interface fluxes belong to cells and interfaces, so
+    // a lane may take its neighbours' values instead of evaluating them on its halo.
+    static constexpr bool LANE_EXCHANGE = true;
 
     // Eq. EulerP with E the total energy per volume: P = (gamma-1)(E - (m u)/2), u = m/rho.
     // Products that feed a sum are fused into it throughout (for this halving the

@@ -38,6 +38,71 @@ __device__ __forceinline__ double dpp_zero(double v)
     return __builtin_bit_cast(double, r);
 }
 
+// A level of a scheme whose per-cell quantities neighbouring lanes share (Euler):
+// each lane evaluates the pressures, pressure ratios and right-interface fluxes of
+// its own P cells only and takes the three it lacks from outside its run -- the
+// pressures of cells -1 and P, the ratio of cell P and the flux through its left
+// interface -- from the neighbouring lanes through DPP.  Every value is the same
+// operation on the same operands as in Sch::level, so the result is identical; a
+// lane evaluates P of each quantity instead of P + 4 pressures, P + 2 ratios and
+// P + 1 fluxes.  Valid where no halo is patched into the level (one-wave tiles off
+// the walls, below the widest level): there the wave's edge lanes, which receive
+// zeros, hold no computed point, just as with the halo gather.
+template <class Sch, int P, bool SEL>
+__device__ __forceinline__ void level_exchange(double (&dst)[Sch::NV][P], const double (&ext)[Sch::NV][P + 2 * Sch::R],
+                                               bool predictor, const Consts &c, const bool (&in)[P])
+{
+    constexpr int NV = Sch::NV, R = Sch::R;
+    static_assert(NV == 3 && R == 2, "laid out for the Euler rule");
+    double pres[P + 2];  // pres[k + 1]: own cell k; pres[0]: cell -1; pres[P + 1]: cell P
+#pragma unroll
+    for (int k = 0; k < P; ++k) pres[k + 1] = Sch::pressure(ext[0][R + k], ext[1][R + k], ext[2][R + k], c);
+    pres[0] = dpp_zero<DPP_WAVE_SHR1>(pres[P]);
+    pres[P + 1] = dpp_zero<DPP_WAVE_SHL1>(pres[1]);
+    double pr[P + 1];  // pr[k]: ratio at cell k, k = 0 .. P
+#pragma unroll
+    for (int k = 0; k < P; ++k) pr[k] = Sch::pratio(pres[k], pres[k + 1], pres[k + 2]);
+    pr[P] = dpp_zero<DPP_WAVE_SHL1>(pr[0]);
+    // The last cell's right-interface flux first: the right neighbour needs it as its
+    // left-interface flux.  The others are evaluated as the update streams over the cells.
+    double flast[3];
+    {
+        const double qb[3] = {ext[0][R + P - 1], ext[1][R + P - 1], ext[2][R + P - 1]};
+        const double qc[3] = {ext[0][R + P], ext[1][R + P], ext[2][R + P]};
+        Sch::flux(qb, qc, pr[P - 1], pr[P], c, flast);
+    }
+    double fprev[3];  // flux through the interface between cells -1 and 0
+#pragma unroll
+    for (int v = 0; v < 3; ++v) fprev[v] = dpp_zero<DPP_WAVE_SHR1>(flast[v]);
+    const double coef = predictor ? c.hlam : c.lam;
+    double val[NV][P];
+#pragma unroll
+    for (int k = 0; k < P; ++k) {
+        double fnext[3];  // flux through the interface between cells k and k + 1
+        if (k == P - 1) {
+#pragma unroll
+            for (int v = 0; v < 3; ++v) fnext[v] = flast[v];
+        } else {
+            const double qb[3] = {ext[0][R + k], ext[1][R + k], ext[2][R + k]};
+            const double qc[3] = {ext[0][R + k + 1], ext[1][R + k + 1], ext[2][R + k + 1]};
+            Sch::flux(qb, qc, pr[k], pr[k + 1], c, fnext);
+        }
+#pragma unroll
+        for (int v = 0; v < 3; ++v) {
+            const double base = predictor ? ext[v][R + k] : dst[v][k];
+            val[v][k] = sw_fma(coef, fprev[v] - fnext[v], base);
+            if (!SEL && in[k]) dst[v][k] = val[v][k];
+            fprev[v] = fnext[v];
+        }
+    }
+    if (SEL) {
+#pragma unroll
+        for (int k = 0; k < P; ++k)
+#pragma unroll
+            for (int v = 0; v < 3; ++v) dst[v][k] = in[k] ? val[v][k] : dst[v][k];
+    }
+}
+
 // One level of a tile: gather the source row with halos, then update the points
 // of the computed set [w/2 - r m, w/2 + r m).  Element k of the wave's lanes is
 // inside for a contiguous range of lanes whose ends take only two values each
@@ -181,6 +246,12 @@ __device__ __forceinline__ void level_step(const TileArgs &a, int g, int NW, int
         int la, lb;
         element_lane_bounds(P, R, INC, SMOD, lo, hi, base, k, la, lb);
         in[k] = lane >= la && lane < lb;
+    }
+    if constexpr (Sch::LANE_EXCHANGE && !MULTI && !WALL) {
+        if (!(s == a.H && a.kind != PH_UP)) {  // the widest level reads the patched outer halo
+            level_exchange<Sch, P, Sch::SELECT_ONE_WAVE>(dst, ext, ODD, a.c, in);
+            return;
+        }
     }
     Sch::template level<P, MULTI || Sch::SELECT_ONE_WAVE>(dst, ext, ODD, a.c, in);
 }
