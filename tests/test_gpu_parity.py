@@ -78,6 +78,11 @@ SMALL = [  # (problem factory, width, threads)
     (lambda: (W.Problem(W.KS, 3072, 421, 2.0 ** -8, 0.5, bc=W.DIRICHLET, bc_left=(0.4, 0, 0),
                         bc_right=(-0.2, 0, 0)), W.fourier_ic(3072, 21)), 1024, 64),
     (lambda: (W.sod_problem(2048, 777), W.sod_ic(2048)), 512, 64),        # P = 8, three variables
+    # Sod on one-wave tiles of 1, 2 and 4 points per lane (lane exchange of pressures, ratios
+    # and fluxes), an odd tile count and remainders
+    (lambda: (W.sod_problem(1280, 641), W.sod_ic(1280)), 256, 64),
+    (lambda: (W.sod_problem(1024, 900), W.sod_ic(1024)), 128, 64),
+    (lambda: (W.sod_problem(768, 333), W.sod_ic(768)), 64, 64),
 ]
 
 
@@ -101,11 +106,14 @@ def test_swept_matches_classic_bitwise_and_oracle(oracle_mod, case):
     assert relerr(swept, oracle_mod.solve(prob, ic)) <= TOL
 
 
+@pytest.mark.parametrize("shape", [(512, 128), (256, 64), (128, 64)])
 @pytest.mark.parametrize("limiter", [0, 1])
-def test_euler_limiter_orientations(oracle_mod, limiter):
+def test_euler_limiter_orientations(oracle_mod, limiter, shape):
+    """Both limiter orientations, on a multi-wave tile (plain rule) and on one-wave tiles
+    (pressures, ratios and fluxes exchanged between lanes)."""
     prob, ic = W.cfg_sod(11)
     prob = prob.with_steps(700)
-    got = gpu_solve(prob, ic, "swept", 512, 128, limiter=limiter)
+    got = gpu_solve(prob, ic, "swept", *shape, limiter=limiter)
     assert np.array_equal(got, oracle_mod.solve(prob, ic, limiter=limiter))
 
 
