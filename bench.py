@@ -561,8 +561,8 @@ def main():
                          "anchors: out-of-cache sizes and a copy; serve: configured and sustainable "
                          "serving; oracle: CPU oracle on all cores and one; kernel, classic-kernel: counter runs")
     ap.add_argument("--max-steps", type=int, default=50_000)
-    ap.add_argument("--kernel-scheme", default="ks", choices=["ks", "heat"],
-                    help="kernel suite: scheme of the profiled Diamond (N = 2^20)")
+    ap.add_argument("--kernel-scheme", default="ks", choices=["ks", "heat", "euler"],
+                    help="kernel suite: scheme of the profiled Diamond (N = 2^20; euler: the Sod tube)")
     ap.add_argument("--kernel-width", type=int, default=0, help="kernel suite: tile width (0 = tuned)")
     ap.add_argument("--kernel-threads", type=int, default=0, help="kernel suite: work-group size (0 = tuned)")
     args = ap.parse_args()
@@ -579,9 +579,14 @@ def main():
         dst = torch.empty_like(src)
         dst.copy_(src)
         torch.cuda.synchronize()
-        prob, ic = W.cfg_sweep({"ks": W.KS, "heat": W.HEAT}[args.kernel_scheme], LOG2N)
+        if args.kernel_scheme == "euler":
+            prob, ic = W.cfg_sod(LOG2N, nsteps=2000)
+        else:
+            prob, ic = W.cfg_sweep({"ks": W.KS, "heat": W.HEAT}[args.kernel_scheme], LOG2N)
         with sw.Plan(prob, args.kernel_width, args.kernel_threads) as plan:
             x = torch.tensor(ic, dtype=torch.float64, device="cuda")
+            if args.kernel_scheme == "euler":
+                plan.swept(x)   # the Diamonds then read edges of a developed Sod state
             us = plan.profile_phase(x, kind=1, reps=args.profile_reps)
             info = plan.info()
         print(json.dumps({"copy_bytes": 2 * src.numel() * 8, "diamond_avg_us": us, "scheme": args.kernel_scheme,

@@ -390,8 +390,8 @@ __device__ __forceinline__ void tile_body(const TileArgs &args, int64_t j, int g
 
 // MAXT bounds the work-group size the kernel is compiled for.  MAXT = 64 is the
 // one-wave tile: the multi-wave path (LDS exchange, barriers) is compiled out,
-// the rows are stored through LDS, and the register allocator is not held to the
-// 1024-lane bound's share of the file.
+// the rows are stored through LDS, and the register allocator is not held to a
+// many-wave bound's share of the register file.
 template <class Sch, int P, int MAXT>
 __global__ __launch_bounds__(MAXT) void swept_tile(TileArgs a)
 {
