@@ -66,7 +66,9 @@ struct Heat {
         for (int k = 0; k < P; ++k) {
             double s = ext[0][k + 2] + ext[0][k];
             val[k] = sw_fma(c.fo, s, c.c0 * ext[0][k + 1]);
-            if (!SEL && in[k]) dst[0][k] = val[k];
+            // Most points of a level lie inside the computed set: the hint lets the
+            // compiler drop the exec-zero skip branches around the masked updates.
+            if (!SEL && __builtin_expect(in[k], 1)) dst[0][k] = val[k];
         }
         if (SEL) {
 #pragma unroll
