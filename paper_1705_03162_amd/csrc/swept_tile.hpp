@@ -173,8 +173,9 @@ __device__ __forceinline__ void level_step(const TileArgs &a, int g, int NW, int
         }
     }
     const int x0 = g * P;  // first tile position of this lane
-    // The tile's outer halo is read by the widest level of a Diamond/Down only.
-    if (s == a.H && a.kind != PH_UP) {
+    // The tile's outer halo is read by the widest level of a Diamond/Down only, once
+    // per launch: the hint keeps the common path free of taken branches.
+    if (__builtin_expect(s == a.H && a.kind != PH_UP, 0)) {
         const bool refl = a.bc == BC_REFLECTIVE;  // heat only: R == 1
         if (x0 < R) {
             if (refl && (a.ends & 1)) {
@@ -248,7 +249,7 @@ __device__ __forceinline__ void level_step(const TileArgs &a, int g, int NW, int
         in[k] = lane >= la && lane < lb;
     }
     if constexpr (Sch::LANE_EXCHANGE && !MULTI && !WALL) {
-        if (!(s == a.H && a.kind != PH_UP)) {  // the widest level reads the patched outer halo
+        if (__builtin_expect(!(s == a.H && a.kind != PH_UP), 1)) {  // the widest level reads the patched halo
             level_exchange<Sch, P, Sch::SELECT_ONE_WAVE>(dst, ext, ODD, a.c, in);
             return;
         }
