@@ -69,7 +69,10 @@ def test_ensemble_each_result_equals_alone(oracle_mod):
         assert np.abs(got - want).max() <= 1e-12 * max(1.0, np.abs(want).max())
 
 
-def test_ensemble_with_euler_and_budget_waves():
+def test_ensemble_with_euler_and_budget_waves(oracle_mod):
+    """Mixed ensemble in budget-limited waves; each result equals the solve alone, and the
+    Sod solves (batched one-wave tiles, pressures, ratios and fluxes exchanged between
+    lanes) equal the oracle bit for bit."""
     probs = mixed_problems(20, seed=2, schemes=(W.HEAT, W.KS, W.EULER), nmax=4096, smax=400)
     budget = max(3 * p.n * p.nvars * 8 for p, _ in probs) * 3   # a few solves per wave
     states = [torch.tensor(ic, dtype=torch.float64, device=DEV) for _, ic in probs]
@@ -78,7 +81,10 @@ def test_ensemble_with_euler_and_budget_waves():
         b.run()
         assert all(b.poll(t) == N.SW_TICKET_DONE for t in tickets)
     for (prob, ic), x in zip(probs, states):
-        assert np.array_equal(x.cpu().numpy(), alone(prob, ic))
+        got = x.cpu().numpy()
+        assert np.array_equal(got, alone(prob, ic))
+        if prob.scheme == W.EULER:
+            assert np.array_equal(got, oracle_mod.solve(prob, ic)), (prob.n, prob.nsteps)
 
 
 def test_served_mix_equals_alone():
