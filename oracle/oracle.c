@@ -1,11 +1,23 @@
 /*
  * CPU oracle: plain classic time-stepping, one level (sub-timestep) at a time,
  * reading the previous level from one buffer and writing the next into another.
- * Test infrastructure only -- see oracle.h.  Every update below is written out
- * from the paper's appendices in the order the equations state it; OpenMP only
- * splits the loop over grid points (no reductions, so the result does not depend
- * on the thread count).  Build with -ffp-contract=off and no fast-math: the
- * only fused operations are the explicit fma() calls.
+ * Test infrastructure only -- see oracle.h.  OpenMP only splits the loop over
+ * grid points (no reductions, so the result does not depend on the thread
+ * count).  Build with -ffp-contract=off and no fast-math: the only fused
+ * operations are the explicit fma() calls.
+ *
+ * Each scheme is written twice:
+ *   literal form   -- the equation as the appendix prints it (after the
+ *                     readings of its typos), evaluated left to right, every
+ *                     product and quotient rounded on its own;
+ *   canonical form -- the same polynomial or formula in one fixed rounding
+ *                     order: products that feed a sum fused into it (C99 fma,
+ *                     one rounding), the KS right-hand side collected by
+ *                     symmetric stencil pair.  The paper fixes no rounding
+ *                     order; this one is frozen, and the GPU library must
+ *                     reproduce it bit for bit.
+ * Exact-arithmetic tests (Fractions, 50-digit mpmath) evaluate one level of the
+ * literal equations and bound both forms' deviation from it.
  */
 #include "oracle.h"
 
@@ -22,8 +34,8 @@
 /* Value of variable v at grid index j, which may lie outside [0, n).
  * Periodic: the stencil at point 0 reaches points n-1, n-2 (Appendix C).
  * Dirichlet: the end states are held at their ends for every (sub)level
- * (Appendix D: "the spatial boundary conditions are these values at their
- * respective ends of the tube"). */
+ * (Appendix D, Eq. SodCond: the spatial boundary values are the two initial
+ * states, each at its own end). */
 static double at(const oracle_problem *p, const double *a, int64_t j, int v)
 {
     const int64_t n = p->n;
@@ -53,6 +65,13 @@ static void heat_level(const oracle_problem *p, const double *cur, double *nxt,
                        double fo, double c0)
 {
     const int64_t n = p->n;
+    if (p->form == ORACLE_FORM_LITERAL) {
+        /* Fo (T_{i+1} + T_{i-1}) + (1 - 2 Fo) T_i, two products and a sum */
+#pragma omp parallel for schedule(static)
+        for (int64_t i = 0; i < n; ++i)
+            nxt[i] = fo * (at(p, cur, i + 1, 0) + at(p, cur, i - 1, 0)) + c0 * cur[i];
+        return;
+    }
 #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; ++i) {
         double s = at(p, cur, i + 1, 0) + at(p, cur, i - 1, 0);
@@ -81,7 +100,23 @@ static void heat_level(const oracle_problem *p, const double *cur, double *nxt,
 /* d1 = 0 and the pair factor is exactly c2 - 4 c4.                           */
 /* ------------------------------------------------------------------------ */
 
-typedef struct { double c1, c4, k1, k0; } ks_consts;   /* k1 = c2 - 4 c4, k0 = 6 c4 - 2 c2 */
+typedef struct {
+    double c1, c4, k1, k0;          /* canonical: 1/(4 dx), c2^2, c2 - 4 c4, 6 c4 - 2 c2 */
+    double four_dx, dx2, dx4;       /* literal: 4 dx, dx^2, dx^4 */
+    int literal;
+} ks_consts;
+
+/* Literal Eq. KSDisc (second difference with -2 v_i): f_i(v), three quotients
+ * summed left to right and negated. */
+static double ks_f_literal(const oracle_problem *p, const double *v, int64_t i, const ks_consts *k)
+{
+    double vm2 = at(p, v, i - 2, 0), vm1 = at(p, v, i - 1, 0), v0 = v[i];
+    double vp1 = at(p, v, i + 1, 0), vp2 = at(p, v, i + 2, 0);
+    double adv = (vp1 * vp1 - vm1 * vm1) / k->four_dx;
+    double diff2 = (vp1 + vm1 - 2.0 * v0) / k->dx2;
+    double diff4 = (vp2 - 4.0 * vp1 + 6.0 * v0 - 4.0 * vm1 + vm2) / k->dx4;
+    return -(adv + diff2 + diff4);
+}
 
 static double ks_g(const oracle_problem *p, const double *v, int64_t i, const ks_consts *k)
 {
@@ -92,24 +127,22 @@ static double ks_g(const oracle_problem *p, const double *v, int64_t i, const ks
     return fma(s1, pair, fma(k->c4, s2, k->k0 * v0));
 }
 
-/* Predictor, Eq. RKm: u^{m+1/2} = u^m + (dt/2) f(u^m) = u^m - (dt/2) g(u^m). */
-static void ks_predictor(const oracle_problem *p, const double *u, double *half,
-                         const ks_consts *k, double hdt)
+/* One RK2 stage: out_i = base_i + coef f_i(src).  Predictor, Eq. RKm:
+ * u^{m+1/2} = u^m + (dt/2) f(u^m); final, Eq. RKf: u^{m+1} = u^m + dt f(u^{m+1/2}).
+ * Canonical: base - coef g with g = -f, one fused multiply-add. */
+static void ks_stage(const oracle_problem *p, const double *src, const double *base, double *out,
+                     const ks_consts *k, double coef)
 {
     const int64_t n = p->n;
+    if (k->literal) {
+#pragma omp parallel for schedule(static)
+        for (int64_t i = 0; i < n; ++i)
+            out[i] = base[i] + coef * ks_f_literal(p, src, i, k);
+        return;
+    }
 #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; ++i)
-        half[i] = fma(-hdt, ks_g(p, u, i, k), u[i]);
-}
-
-/* Final, Eq. RKf: u^{m+1} = u^m + dt f(u^{m+1/2}) = u^m - dt g(u^{m+1/2}). */
-static void ks_final(const oracle_problem *p, const double *u, const double *half,
-                     double *nxt, const ks_consts *k, double dt)
-{
-    const int64_t n = p->n;
-#pragma omp parallel for schedule(static)
-    for (int64_t i = 0; i < n; ++i)
-        nxt[i] = fma(-dt, ks_g(p, half, i, k), u[i]);
+        out[i] = fma(-coef, ks_g(p, src, i, k), base[i]);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -117,7 +150,7 @@ static void ks_final(const oracle_problem *p, const double *u, const double *hal
 /* per volume; F(Q) = (rho u, rho u^2 + P, u (E + P)); P from Eq. EulerP.      */
 /* ------------------------------------------------------------------------ */
 
-typedef struct { double gm1, gamma; int limiter; } euler_consts;
+typedef struct { double gm1, gamma; int limiter, literal; } euler_consts;
 
 /* Eq. EulerP: P = (gamma - 1)(E - rho u^2 / 2), evaluated as (m u)/2 with u = m/rho.
  * Products that feed a sum are fused into it (C99 fma) throughout this scheme; for
@@ -186,6 +219,53 @@ static void interface_flux(const double qa[3], const double qb[3], const double 
         flux[v] = 0.5 * fma(r_sp, ql[v] - qr[v], fr[v] + fl[v]);
 }
 
+/* Literal form of the same interface flux: Eq. EulerP as P = (gamma-1)(E - rho u^2/2)
+ * with u = m/rho, Eq. EulerF as (m, rho u^2 + P, u (E + P)), the Roe average and
+ * spectral radius as printed, Flux = (F(Q^R) + F(Q^L) + r_sp (Q^L - Q^R)) / 2; every
+ * product and quotient rounded on its own, sums left to right. */
+static double pressure_literal(const double q[3], const euler_consts *c)
+{
+    double u = q[1] / q[0];
+    return c->gm1 * (q[2] - q[0] * u * u / 2.0);
+}
+
+static void physical_flux_literal(const double q[3], const euler_consts *c, double f[3])
+{
+    double u = q[1] / q[0];
+    double pr = pressure_literal(q, c);
+    f[0] = q[1];
+    f[1] = q[0] * u * u + pr;
+    f[2] = u * (q[2] + pr);
+}
+
+static void interface_flux_literal(const double qa[3], const double qb[3], const double qc[3],
+                                   const double qd[3], const euler_consts *c, double flux[3])
+{
+    double pa = pressure_literal(qa, c), pb = pressure_literal(qb, c);
+    double pc = pressure_literal(qc, c), pd = pressure_literal(qd, c);
+    double pr_b = (pc - pb) / (pb - pa);        /* Eq. Pratio at cell b */
+    double pr_c = (pd - pc) / (pc - pb);        /* and at cell c */
+    /* the ratio each side's limiter takes (reading of Eqs. limitleft/limitright) */
+    double tl = c->limiter == 0 ? pr_b : 1.0 / pr_b;
+    double tr = c->limiter == 0 ? 1.0 / pr_c : pr_c;
+    double ql[3], qr[3];
+    for (int v = 0; v < 3; ++v) {
+        ql[v] = (tl > 0.0 && tl < INFINITY) ? qb[v] + min_d(tl, 1.0) / 2.0 * (qc[v] - qb[v]) : qb[v];
+        qr[v] = (tr > 0.0 && tr < INFINITY) ? qc[v] + min_d(tr, 1.0) / 2.0 * (qb[v] - qc[v]) : qc[v];
+    }
+    double fl[3], fr[3];
+    physical_flux_literal(ql, c, fl);
+    physical_flux_literal(qr, c, fr);
+    double ul = ql[1] / ql[0], ur = qr[1] / qr[0];
+    double rho_sp = sqrt(ql[0] * qr[0]);
+    double u_sp = (sqrt(ql[0]) * ul + sqrt(qr[0]) * ur) / (sqrt(ql[0]) + sqrt(qr[0]));
+    double e_sp = (sqrt(ql[0]) * ql[2] + sqrt(qr[0]) * qr[2]) / (sqrt(ql[0]) + sqrt(qr[0]));
+    double p_sp = c->gm1 * (e_sp - rho_sp * u_sp * u_sp / 2.0);
+    double r_sp = sqrt(c->gamma * p_sp / rho_sp) + fabs(u_sp);
+    for (int v = 0; v < 3; ++v)
+        flux[v] = 0.5 * (fr[v] + fl[v] + r_sp * (ql[v] - qr[v]));
+}
+
 static void load_cell(const oracle_problem *p, const double *q, int64_t j, double out[3])
 {
     for (int v = 0; v < 3; ++v) out[v] = at(p, q, j, v);
@@ -203,6 +283,13 @@ static void euler_stage(const oracle_problem *p, const double *src, const double
         double q[5][3];
         for (int k = 0; k < 5; ++k) load_cell(p, src, i - 2 + k, q[k]);
         double fm[3], fp[3];
+        if (c->literal) {
+            interface_flux_literal(q[0], q[1], q[2], q[3], c, fm);   /* i - 1/2 */
+            interface_flux_literal(q[1], q[2], q[3], q[4], c, fp);   /* i + 1/2 */
+            for (int v = 0; v < 3; ++v)
+                out[(int64_t)v * n + i] = base[(int64_t)v * n + i] + coef * (fm[v] - fp[v]);
+            continue;
+        }
         interface_flux(q[0], q[1], q[2], q[3], c, fm);   /* i - 1/2 */
         interface_flux(q[1], q[2], q[3], q[4], c, fp);   /* i + 1/2 */
         for (int v = 0; v < 3; ++v)
@@ -216,6 +303,34 @@ static void euler_stage(const oracle_problem *p, const double *src, const double
 
 static int nvars_of(int scheme) { return scheme == ORACLE_EULER ? 3 : 1; }
 
+/* Constants of each scheme, computed once per solve in the order written here. */
+static void heat_consts(const oracle_problem *p, double *fo, double *c0)
+{
+    *fo = (p->alpha * p->dt) / (p->dx * p->dx);
+    *c0 = 1.0 - 2.0 * *fo;
+}
+
+static void make_ks_consts(const oracle_problem *p, ks_consts *k)
+{
+    double c2 = 1.0 / (p->dx * p->dx);
+    k->c1 = 1.0 / (4.0 * p->dx);
+    k->c4 = c2 * c2;
+    k->k1 = c2 - 4.0 * k->c4;
+    k->k0 = 6.0 * k->c4 - 2.0 * c2;
+    k->four_dx = 4.0 * p->dx;
+    k->dx2 = p->dx * p->dx;
+    k->dx4 = k->dx2 * k->dx2;
+    k->literal = p->form == ORACLE_FORM_LITERAL;
+}
+
+static void make_euler_consts(const oracle_problem *p, euler_consts *c)
+{
+    c->gm1 = p->gamma - 1.0;
+    c->gamma = p->gamma;
+    c->limiter = p->limiter;
+    c->literal = p->form == ORACLE_FORM_LITERAL;
+}
+
 static int valid(const oracle_problem *p)
 {
     if (!p) return 0;
@@ -223,6 +338,7 @@ static int valid(const oracle_problem *p)
     if (p->bc != ORACLE_PERIODIC && p->bc != ORACLE_DIRICHLET && p->bc != ORACLE_REFLECTIVE) return 0;
     if (p->bc == ORACLE_REFLECTIVE && (p->scheme != ORACLE_HEAT || p->n < 2)) return 0;
     if (p->n < 1 || p->nsteps < 0) return 0;
+    if (p->form != ORACLE_FORM_CANONICAL && p->form != ORACLE_FORM_LITERAL) return 0;
     if (!(p->dt > 0.0) || !(p->dx > 0.0)) return 0;
     return 1;
 }
@@ -261,30 +377,24 @@ int oracle_solve_timed(const oracle_problem *p, double *state, int nthreads, dou
 
     double t0 = now_s();
     if (p->scheme == ORACLE_HEAT) {
-        double fo = (p->alpha * p->dt) / (p->dx * p->dx);
-        double c0 = 1.0 - 2.0 * fo;
+        double fo, c0;
+        heat_consts(p, &fo, &c0);
         for (int64_t m = 0; m < p->nsteps; ++m) {
             heat_level(p, a, b, fo, c0);
             double *t = a; a = b; b = t;
         }
     } else if (p->scheme == ORACLE_KS) {
-        double c2 = 1.0 / (p->dx * p->dx);
         ks_consts k;
-        k.c1 = 1.0 / (4.0 * p->dx);
-        k.c4 = c2 * c2;
-        k.k1 = c2 - 4.0 * k.c4;
-        k.k0 = 6.0 * k.c4 - 2.0 * c2;
+        make_ks_consts(p, &k);
         double hdt = 0.5 * p->dt;
         for (int64_t m = 0; m < p->nsteps; ++m) {
-            ks_predictor(p, a, h, &k, hdt);
-            ks_final(p, a, h, b, &k, p->dt);
+            ks_stage(p, a, a, h, &k, hdt);      /* predictor */
+            ks_stage(p, h, a, b, &k, p->dt);    /* final */
             double *t = a; a = b; b = t;
         }
     } else {
         euler_consts c;
-        c.gm1 = p->gamma - 1.0;
-        c.gamma = p->gamma;
-        c.limiter = p->limiter;
+        make_euler_consts(p, &c);
         double lam = p->dt / p->dx;
         double hlam = 0.5 * lam;
         for (int64_t m = 0; m < p->nsteps; ++m) {
@@ -310,11 +420,36 @@ int oracle_solve(const oracle_problem *p, double *state, int nthreads)
     return oracle_solve_timed(p, state, nthreads, 0);
 }
 
+int oracle_stage(const oracle_problem *p, int final_stage, const double *src, const double *base,
+                 double *out, int nthreads)
+{
+    if (!valid(p) || !src || !base || !out) return -1;
+    if (final_stage != 0 && final_stage != 1) return -1;
+    if (p->scheme == ORACLE_HEAT && final_stage) return -1;
+    oracle_threads(nthreads);
+    if (p->scheme == ORACLE_HEAT) {
+        double fo, c0;
+        heat_consts(p, &fo, &c0);
+        heat_level(p, src, out, fo, c0);
+    } else if (p->scheme == ORACLE_KS) {
+        ks_consts k;
+        make_ks_consts(p, &k);
+        ks_stage(p, src, base, out, &k, final_stage ? p->dt : 0.5 * p->dt);
+    } else {
+        euler_consts c;
+        make_euler_consts(p, &c);
+        double lam = p->dt / p->dx;
+        euler_stage(p, src, base, out, final_stage ? lam : 0.5 * lam, &c);
+    }
+    return 0;
+}
+
 void oracle_euler_flux(const double cells[4][3], double gamma, int limiter, double flux[3])
 {
     euler_consts c;
     c.gm1 = gamma - 1.0;
     c.gamma = gamma;
     c.limiter = limiter;
+    c.literal = 0;
     interface_flux(cells[0], cells[1], cells[2], cells[3], &c, flux);
 }
