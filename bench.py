@@ -35,12 +35,18 @@ METRIC = "FP64 point-updates/s (swept vs classic, 1 GPU) + batched p50/p99 solve
 PEAK_FP64_TFLOPS = 78.6   # MI355X published FP64 vector peak
 N_SW_ENOTREADY = -6       # include/swept.h: ticket still running
 PEAK_HBM_GBS = 8000.0
-# Algorithmic FP64 operations per point per sub-step level: each add, subtract and
-# multiply of the update as the paper writes it, independent of how the kernel
-# fuses or regroups them.  Heat (Eq. Heatdisc): 2 adds, 2 multiplies.  KS (Eq.
-# KSDisc with the four-point terms in symmetric pairs, plus the RK stage): 16 in f,
-# 2 in u + c f.
-FLOPS_PER_POINT_LEVEL = {W.HEAT: 4, W.KS: 18}
+# Algorithmic FP64 operations per point per sub-step level: each add, subtract,
+# multiply, divide and square root of the update as the paper writes it, each
+# counted once, independent of how the kernel fuses or regroups them.  Heat (Eq.
+# Heatdisc): 2 adds, 2 multiplies.  KS (Eq. KSDisc with the four-point terms in
+# symmetric pairs, plus the RK stage): 16 in f, 2 in u + c f.  Euler (Appendix D,
+# per cell and sub-step with each interface flux evaluated once): pressure 6,
+# pressure ratio 3, interface flux 80 (reciprocal ratio and two reconstructions 21,
+# two physical fluxes 22, Roe average 13, P_sp 5, spectral radius 4, flux 15),
+# stage 9 = 98, of them 8 divisions and 4 square roots, each counted as one
+# operation although gfx950 evaluates a binary64 division or root as a sequence.
+FLOPS_PER_POINT_LEVEL = {W.HEAT: 4, W.KS: 18, W.EULER: 98}
+SUBSTEPS = {W.HEAT: 1, W.KS: 2, W.EULER: 2}
 # Algorithmic HBM bytes per point-update of the classic decomposition (state read
 # and written once per sub-step: heat 8r+8w; KS predictor 8r+8w, final 16r+8w;
 # Euler 3 variables over two sub-steps).
@@ -307,7 +313,7 @@ def suite_sweep(schemes, log2ns, max_steps):
                     "e2e_swept": upd / e2e_s, "e2e_classic": upd / e2e_c,
                     "classic_hbm_roofline": roof, "swept_over_classic_roofline": rs / roof}
             if scheme in FLOPS_PER_POINT_LEVEL:
-                ops = rs * FLOPS_PER_POINT_LEVEL[scheme] * (2 if scheme == W.KS else 1)
+                ops = rs * FLOPS_PER_POINT_LEVEL[scheme] * SUBSTEPS[scheme]
                 line["swept_fp64_tflops"] = ops / 1e12
                 line["swept_frac_fp64_peak"] = ops / (PEAK_FP64_TFLOPS * 1e12)
             print(json.dumps(line), flush=True)
@@ -589,9 +595,12 @@ def main():
                 plan.swept(x)   # the Diamonds then read edges of a developed Sod state
             us = plan.profile_phase(x, kind=1, reps=args.profile_reps)
             info = plan.info()
+        flops = prob.n * info["levels_per_phase"] * FLOPS_PER_POINT_LEVEL[prob.scheme]
         print(json.dumps({"copy_bytes": 2 * src.numel() * 8, "diamond_avg_us": us, "scheme": args.kernel_scheme,
                           "width": info["width"], "threads": info["threads"],
                           "levels_per_phase": info["levels_per_phase"], "n": prob.n,
+                          "flops_per_launch": flops, "tflops": flops / (us * 1e-6) / 1e12,
+                          "frac_fp64_peak": flops / (us * 1e-6) / 1e12 / PEAK_FP64_TFLOPS,
                           "kernel_digest": kernel_digest()}), flush=True)
         return
     if args.suite == "classic-kernel":

@@ -5,7 +5,7 @@
  * The problem statement follows the paper (Magee & Niemeyer, "Accelerating
  * solutions of one-dimensional unsteady PDEs with GPU-based swept time-space
  * decomposition"): a scheme, a grid of n points, dt and dx, a number of
- * timesteps and a boundary type (Sec. 3.1 experimental method, Sec. 4.2 test
+ * timesteps and a boundary type (Sec. 4.1 experimental method, Sec. 5.2 test
  * cases, Appendices B-D).  Schemes:
  *   SW_HEAT   heat equation, forward-time central-space     (Appendix B, Eq. Heatdisc)
  *   SW_KS     Kuramoto-Sivashinsky, 5-point central + RK2   (Appendix C, Eqs. KSDisc, RKm, RKf)
@@ -86,13 +86,18 @@ typedef struct {
  * most 512 with 8 or more points per lane, Euler: 512, and 256 with 8 points per
  * lane); width = points per swept tile = points_per_lane * threads, with
  * points_per_lane in {1, 2, 4, 8, 16} and at least the stencil radius (Euler:
- * at most 8).  Zeros ask for the tuned or default choice. */
+ * at most 8).  classic_threads = work-group size of the classic kernel (one
+ * point per lane; a multiple of 64 in [64, 1024]); the paper takes the best time
+ * over block sizes (Sec. 4.1, experimental method), and the tuning table holds
+ * the measured best per scheme and size class.  Zeros ask for the tuned or
+ * default choice (classic default 256). */
 #define SW_TUNE_NO_GRAPH  1   /* enqueue kernels one by one instead of replaying a HIP graph */
 #define SW_TUNE_CHECK_NAN 2   /* after a solve, synchronise and report SW_ENAN on non-finite output */
 typedef struct {
     int32_t width;
     int32_t threads;
-    int32_t flags;         /* SW_TUNE_* */
+    int32_t flags;           /* SW_TUNE_* */
+    int32_t classic_threads;
 } sw_tuning;
 
 typedef struct {
@@ -103,7 +108,7 @@ typedef struct {
     int32_t substeps;         /* S: sub-steps per timestep (1 heat, 2 KS/Euler) */
     int32_t nvars;            /* variables per point */
     int32_t swept_ok;         /* 1 if swept_solve can run (width divides n) */
-    int32_t pad;
+    int32_t classic_threads;  /* work-group size of the classic kernel */
     int64_t nodes;            /* K = n / w tiles per phase */
     int64_t levels;           /* S * nsteps sub-step levels */
     int64_t levels_per_phase; /* H = w / (2 r) */
@@ -124,14 +129,14 @@ int swept_plan(const sw_problem *problem, const sw_tuning *tuning, sw_plan **out
 /* Geometry and launch counts of a plan. */
 int swept_plan_info(const sw_plan *plan, sw_plan_info *out);
 
-/* Swept decomposition (Sec. 3.2-3.3): an Up-triangle launch, alternating-offset
+/* Swept decomposition (Sec. 4.2-4.3): an Up-triangle launch, alternating-offset
  * Diamond launches, a Down-triangle launch, plus one Up/Down pair for a
  * remainder of fewer levels than a phase.  Each tile advances w/(2r) levels per
  * launch in on-chip memory and exchanges only its edges through HBM.
  * SW_EUNSUPPORTED if no legal width divides n (classic_solve still works). */
 int swept_solve(sw_plan *plan, double *d_state, void *hip_stream);
 
-/* Classic decomposition (Sec. 4.1, the Classic listing): one kernel launch per
+/* Classic decomposition (Sec. 5.1, the Classic listing): one kernel launch per
  * sub-timestep, ping-ponging through global memory. */
 int classic_solve(sw_plan *plan, double *d_state, void *hip_stream);
 

@@ -48,10 +48,10 @@ class Plan:
     """A validated problem with its tile shape, scratch memory and cached graphs."""
 
     def __init__(self, problem, width: int = 0, threads: int = 0, flags: int = 0,
-                 limiter: int = 0):
+                 limiter: int = 0, classic_threads: int = 0):
         self.problem = problem
         self._p = problem_struct(problem, limiter)
-        tun = N.SwTuning(int(width), int(threads), int(flags))
+        tun = N.SwTuning(int(width), int(threads), int(flags), int(classic_threads))
         h = ctypes.c_void_p()
         N.check(N.lib().swept_plan(ctypes.byref(self._p), ctypes.byref(tun), ctypes.byref(h)),
                 "swept_plan")
@@ -60,7 +60,7 @@ class Plan:
     def info(self) -> dict:
         i = N.SwPlanInfo()
         N.check(N.lib().swept_plan_info(self._h, ctypes.byref(i)), "swept_plan_info")
-        return {k: getattr(i, k) for k, _ in N.SwPlanInfo._fields_ if k != "pad"}
+        return {k: getattr(i, k) for k, _ in N.SwPlanInfo._fields_}
 
     def swept(self, state, stream=None):
         N.check(N.lib().swept_solve(self._h, _state_ptr(state, self.problem),
@@ -99,16 +99,14 @@ class Plan:
             pass
 
 
-def swept_plan(problem, width: int = 0, threads: int = 0, flags: int = 0, limiter: int = 0) -> Plan:
-    return Plan(problem, width, threads, flags, limiter)
+def swept_plan(problem, width: int = 0, threads: int = 0, flags: int = 0, limiter: int = 0,
+               classic_threads: int = 0) -> Plan:
+    return Plan(problem, width, threads, flags, limiter, classic_threads)
 
 
 def swept_solve(plan: Plan, state, stream=None):
     return plan.swept(state, stream)
 
-
-def classic_solve(plan: Plan, state, stream=None):
-    return plan.classic(state, stream)
 
 
 class Batch:

@@ -34,7 +34,8 @@ class SwProblem(ctypes.Structure):
 
 
 class SwTuning(ctypes.Structure):
-    _fields_ = [("width", ctypes.c_int32), ("threads", ctypes.c_int32), ("flags", ctypes.c_int32)]
+    _fields_ = [("width", ctypes.c_int32), ("threads", ctypes.c_int32), ("flags", ctypes.c_int32),
+                ("classic_threads", ctypes.c_int32)]
 
 
 class SwPlanInfo(ctypes.Structure):
@@ -42,7 +43,7 @@ class SwPlanInfo(ctypes.Structure):
         ("width", ctypes.c_int32), ("threads", ctypes.c_int32),
         ("points_per_lane", ctypes.c_int32), ("radius", ctypes.c_int32),
         ("substeps", ctypes.c_int32), ("nvars", ctypes.c_int32),
-        ("swept_ok", ctypes.c_int32), ("pad", ctypes.c_int32),
+        ("swept_ok", ctypes.c_int32), ("classic_threads", ctypes.c_int32),
         ("nodes", ctypes.c_int64), ("levels", ctypes.c_int64),
         ("levels_per_phase", ctypes.c_int64), ("full_phases", ctypes.c_int64),
         ("remainder", ctypes.c_int64), ("swept_launches", ctypes.c_int64),

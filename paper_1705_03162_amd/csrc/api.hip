@@ -173,10 +173,11 @@ int enqueue_classic(sw_plan *p, double *state, int64_t steps, int64_t step0, hip
             const bool even = ((step0 + m) & 1) == 0;
             const double *src = even ? state : p->d_tmp;
             double *dst = even ? p->d_tmp : state;
-            e = launch_classic_level(g.scheme, src, dst, g.n, dir, 0, p->consts, st);
+            e = launch_classic_level(g.scheme, src, dst, g.n, dir, 0, p->consts, g.classic_threads, st);
         } else {
-            e = launch_classic_level(g.scheme, state, p->d_tmp, g.n, dir, 1, p->consts, st);
-            if (e == hipSuccess) e = launch_classic_level(g.scheme, p->d_tmp, state, g.n, dir, 0, p->consts, st);
+            e = launch_classic_level(g.scheme, state, p->d_tmp, g.n, dir, 1, p->consts, g.classic_threads, st);
+            if (e == hipSuccess)
+                e = launch_classic_level(g.scheme, p->d_tmp, state, g.n, dir, 0, p->consts, g.classic_threads, st);
         }
         if (e != hipSuccess) return hip_fail(e, "classic kernel launch");
     }
@@ -266,6 +267,10 @@ int swept_plan(const sw_problem *problem, const sw_tuning *tuning, sw_plan **out
     if ((rc = make_geom(*problem, width, threads, &g, &err))) return fail(rc, err);
     if (tuning && tuning->width && !g.swept_ok)
         return fail(SW_EINVAL, "tile width does not divide n");
+    int ct = tuning ? tuning->classic_threads : 0;
+    if (ct == 0 && !tuned_classic_threads(*problem, &ct)) ct = 256;
+    if (!legal_threads(ct)) return fail(SW_EINVAL, "classic_threads must be a multiple of 64 in [64, 1024]");
+    g.classic_threads = ct;
     sw_plan *p = new (std::nothrow) sw_plan();
     if (!p) return fail(SW_ENOMEM, "plan allocation failed");
     p->prob = *problem;
@@ -285,6 +290,7 @@ int swept_plan_info(const sw_plan *p, sw_plan_info *out)
     std::memset(&i, 0, sizeof(i));
     i.width = g.w; i.threads = g.threads; i.points_per_lane = g.P;
     i.radius = g.r; i.substeps = g.S; i.nvars = g.nv; i.swept_ok = g.swept_ok ? 1 : 0;
+    i.classic_threads = g.classic_threads;
     i.nodes = g.K; i.levels = g.levels; i.levels_per_phase = g.H;
     i.full_phases = g.Q; i.remainder = g.rem;
     i.swept_launches = (int64_t)p->phases.size();

@@ -11,10 +11,12 @@ namespace sw {
 
 namespace {
 
-// Classic: one thread per point, one launch per sub-step (Sec. 4.1).  For the
+// Classic: one thread per point, one launch per sub-step (Sec. 5.1).  For the
 // final RK2 stage `dst` holds u^m and is updated in place (the listing's +=).
-template <class Sch>
-__global__ __launch_bounds__(256) void classic_level(const double *__restrict__ src, double *dst,
+// MAXT bounds the work-group size it is compiled for (256, or 1024 for larger
+// blocks, which leaves each lane fewer registers).
+template <class Sch, int MAXT>
+__global__ __launch_bounds__(MAXT) void classic_level(const double *__restrict__ src, double *dst,
                                                      int64_t n, int bc, int predictor, Consts c)
 {
     constexpr int NV = Sch::NV, R = Sch::R;
@@ -77,17 +79,24 @@ hipError_t launch_swept_phase(int scheme, int P, int threads, const TileArgs &a,
     return swept_phase_for<Euler>(P, threads, a, st);
 }
 
-hipError_t launch_classic_level(int scheme, const double *src, double *dst, int64_t n, int bc,
-                                int predictor, const Consts &c, hipStream_t st)
+template <class Sch>
+void classic_launch_t(const double *src, double *dst, int64_t n, int bc, int predictor, const Consts &c,
+                      int T, hipStream_t st)
 {
-    const int T = 256;
     const unsigned blocks = (unsigned)((n + T - 1) / T);
-    if (scheme == 0)
-        hipLaunchKernelGGL(classic_level<Heat>, dim3(blocks), dim3(T), 0, st, src, dst, n, bc, predictor, c);
-    else if (scheme == 1)
-        hipLaunchKernelGGL(classic_level<KS>, dim3(blocks), dim3(T), 0, st, src, dst, n, bc, predictor, c);
+    if (T <= 256)
+        hipLaunchKernelGGL((classic_level<Sch, 256>), dim3(blocks), dim3(T), 0, st, src, dst, n, bc, predictor, c);
     else
-        hipLaunchKernelGGL(classic_level<Euler>, dim3(blocks), dim3(T), 0, st, src, dst, n, bc, predictor, c);
+        hipLaunchKernelGGL((classic_level<Sch, 1024>), dim3(blocks), dim3(T), 0, st, src, dst, n, bc, predictor, c);
+}
+
+hipError_t launch_classic_level(int scheme, const double *src, double *dst, int64_t n, int bc,
+                                int predictor, const Consts &c, int threads, hipStream_t st)
+{
+    if (threads < 64 || threads > 1024 || threads % 64 != 0) return hipErrorInvalidValue;
+    if (scheme == 0) classic_launch_t<Heat>(src, dst, n, bc, predictor, c, threads, st);
+    else if (scheme == 1) classic_launch_t<KS>(src, dst, n, bc, predictor, c, threads, st);
+    else classic_launch_t<Euler>(src, dst, n, bc, predictor, c, threads, st);
     return hipGetLastError();
 }
 

@@ -10,9 +10,10 @@ namespace sw {
 // One swept phase: K work-groups of `threads` lanes, P points per lane.
 hipError_t launch_swept_phase(int scheme, int P, int threads, const TileArgs &a, hipStream_t st);
 
-// One classic sub-step over n points: src -> dst (in place on dst for a final RK2 stage).
+// One classic sub-step over n points: src -> dst (in place on dst for a final RK2 stage),
+// in work-groups of `threads` lanes (a multiple of 64 in [64, 1024]).
 hipError_t launch_classic_level(int scheme, const double *src, double *dst, int64_t n, int bc,
-                                int predictor, const Consts &c, hipStream_t st);
+                                int predictor, const Consts &c, int threads, hipStream_t st);
 
 // One phase of many independent solves: items[i] = (solve index into desc, tile).
 // global_phase >= 0 runs that phase for every solve, -1 each solve's own phase.

@@ -1,7 +1,7 @@
 // Host-side plan geometry: problem validation, canonical constants, legal tile
 // shapes and the launch sequence of a swept solve.
 //
-// Launch sequence (Sec. 3.2): an Up triangle, then Diamonds at alternating
+// Launch sequence (Sec. 4.2): an Up triangle, then Diamonds at alternating
 // offsets (0 and w/2, the zig-zag of the node locations), then a Down triangle
 // that completes a full level; each phase advances H = w/(2r) levels.  A final
 // remainder of h < H levels is done with one more Up/Down pair whose Up stops at
@@ -28,6 +28,7 @@ struct Geom {
     int scheme = 0, bc = 0, r = 1, S = 1, nv = 1;
     int64_t n = 0, nsteps = 0, levels = 0;
     int w = 0, threads = 0, P = 0, NW = 0, H = 0, E = 0;
+    int classic_threads = 256;   // work-group size of the classic kernel
     int64_t K = 0, Q = 0, rem = 0;
     bool swept_ok = false;
     int64_t edge_doubles = 0;

@@ -5,7 +5,7 @@
 // three schemes compiling in parallel.
 //
 // One work-group is one node of the swept rule (the paper's Shared variant maps
-// a node to a block, Sec. 4.1), but the two-row working array lives in VGPRs
+// a node to a block, Sec. 5.1), but the two-row working array lives in VGPRs
 // instead of shared memory: lane g owns P consecutive points of both rows.  Per
 // level a lane needs r points of the source row from each neighbouring lane;
 // inside a wave they arrive through DPP row moves across the whole wave
@@ -111,7 +111,7 @@ __device__ __forceinline__ void level_exchange(double (&dst)[Sch::NV][P], const 
 // (after publishing its boundary values for its neighbours), which recovers most
 // of the idle half of a triangle in multi-wave tiles.
 template <class Sch, int P, bool ODD, bool MULTI, bool WALL, bool INC, int SMOD>
-__device__ __forceinline__ void level_step(const TileArgs &a, int g, int NW, int s, int m,
+__device__ __forceinline__ void level_step(const TileArgs &a, int g, int NW, int s, int m, int org,
                                            const double (&src)[Sch::NV][P], double (&dst)[Sch::NV][P],
                                            const double (&hl)[Sch::NV][Sch::R],
                                            const double (&hr)[Sch::NV][Sch::R],
@@ -138,8 +138,10 @@ __device__ __forceinline__ void level_step(const TileArgs &a, int g, int NW, int
         __syncthreads();
     }
     const int half = a.w >> 1;
-    const int lo = __builtin_amdgcn_readfirstlane(half - R * m);
-    const int hi = __builtin_amdgcn_readfirstlane(half + R * m);
+    // the computed set relative to the first point the lanes hold (org: 0 for the whole
+    // tile, w/2 - 32 P for a one-wave layout packed around the tile centre)
+    const int lo = __builtin_amdgcn_readfirstlane(half - R * m - org);
+    const int hi = __builtin_amdgcn_readfirstlane(half + R * m - org);
     // first lane of this wave (a one-wave tile is lane 0 onwards)
     const int base = MULTI ? __builtin_amdgcn_readfirstlane(g & ~63) : 0;
     if (MULTI) {
@@ -172,7 +174,7 @@ __device__ __forceinline__ void level_step(const TileArgs &a, int g, int NW, int
             for (int i = 1; i < R; ++i) ext[v][R + 1 + i] = dpp_zero<DPP_WAVE_SHL1>(ext[v][R + i]);
         }
     }
-    const int x0 = g * P;  // first tile position of this lane
+    const int x0 = org + g * P;  // first tile position of this lane
     // The tile's outer halo is read by the widest level of a Diamond/Down only, once
     // per launch: the hint keeps the common path free of taken branches.
     if (__builtin_expect(s == a.H && a.kind != PH_UP, 0)) {
@@ -257,12 +259,12 @@ __device__ __forceinline__ void level_step(const TileArgs &a, int g, int NW, int
     Sch::template level<P, MULTI || Sch::SELECT_ONE_WAVE>(dst, ext, ODD, a.c, in);
 }
 
-// Levels s0 + U, s0 + U + 1, ... of one aligned group (s0 = 1 mod G, so the
+// Levels s0 + U, s0 + U + 1, ... of one aligned group (s0 = A mod G, so the
 // row parity and the residues of the computed set are compile-time).  m = s for
 // a widening segment, m = mtop - s for a narrowing one.
-template <class Sch, int P, bool MULTI, bool WALL, bool INC, int U, int G>
+template <class Sch, int P, bool MULTI, bool WALL, bool INC, int A, int U, int G>
 __device__ __forceinline__ void run_group(const TileArgs &a, int g, int NW, int s0, int s_last, int mtop,
-                                          bool full, double (&r0)[Sch::NV][P], double (&r1)[Sch::NV][P],
+                                          int org, bool full, double (&r0)[Sch::NV][P], double (&r1)[Sch::NV][P],
                                           const double (&hl)[Sch::NV][Sch::R],
                                           const double (&hr)[Sch::NV][Sch::R],
                                           double (*xch)[16][2][Sch::NV][Sch::R])
@@ -271,30 +273,31 @@ __device__ __forceinline__ void run_group(const TileArgs &a, int g, int NW, int 
         const int s = s0 + U;
         if (full || s <= s_last) {
             const int m = INC ? s : mtop - s;
-            constexpr int SMOD = (1 + U) % G;
-            if constexpr (((1 + U) & 1) != 0)
-                level_step<Sch, P, true, MULTI, WALL, INC, SMOD>(a, g, NW, s, m, r0, r1, hl, hr, xch);
+            constexpr int SMOD = (A + U) % G;
+            if constexpr (((A + U) & 1) != 0)
+                level_step<Sch, P, true, MULTI, WALL, INC, SMOD>(a, g, NW, s, m, org, r0, r1, hl, hr, xch);
             else
-                level_step<Sch, P, false, MULTI, WALL, INC, SMOD>(a, g, NW, s, m, r1, r0, hl, hr, xch);
-            run_group<Sch, P, MULTI, WALL, INC, U + 1, G>(a, g, NW, s0, s_last, mtop, full, r0, r1, hl, hr, xch);
+                level_step<Sch, P, false, MULTI, WALL, INC, SMOD>(a, g, NW, s, m, org, r1, r0, hl, hr, xch);
+            run_group<Sch, P, MULTI, WALL, INC, A, U + 1, G>(a, g, NW, s0, s_last, mtop, org, full, r0, r1, hl,
+                                                             hr, xch);
         }
     }
 }
 
-// Levels [s_first, s_last] (s_first = 1 mod G) in full groups plus one partial group.
-template <class Sch, int P, bool MULTI, bool WALL, bool INC>
+// Levels [s_first, s_last] (s_first = A mod G) in full groups plus one partial group.
+template <class Sch, int P, bool MULTI, bool WALL, bool INC, int A = 1>
 __device__ __forceinline__ void run_segment(const TileArgs &a, int g, int NW, int s_first, int s_last,
                                             int mtop, double (&r0)[Sch::NV][P], double (&r1)[Sch::NV][P],
                                             const double (&hl)[Sch::NV][Sch::R],
                                             const double (&hr)[Sch::NV][Sch::R],
-                                            double (*xch)[16][2][Sch::NV][Sch::R])
+                                            double (*xch)[16][2][Sch::NV][Sch::R], int org = 0)
 {
     constexpr int G = group_len(P, Sch::R);
     int s0 = s_first;
     for (; s0 + G - 1 <= s_last; s0 += G)
-        run_group<Sch, P, MULTI, WALL, INC, 0, G>(a, g, NW, s0, s_last, mtop, true, r0, r1, hl, hr, xch);
+        run_group<Sch, P, MULTI, WALL, INC, A, 0, G>(a, g, NW, s0, s_last, mtop, org, true, r0, r1, hl, hr, xch);
     if (s0 <= s_last)
-        run_group<Sch, P, MULTI, WALL, INC, 0, G>(a, g, NW, s0, s_last, mtop, false, r0, r1, hl, hr, xch);
+        run_group<Sch, P, MULTI, WALL, INC, A, 0, G>(a, g, NW, s0, s_last, mtop, org, false, r0, r1, hl, hr, xch);
 }
 
 template <class Sch, int P, bool MULTI, bool WALL>
@@ -314,92 +317,252 @@ __device__ __forceinline__ void run_levels(const TileArgs &a, int g, int NW, dou
     }
 }
 
-// One-wave tiles store their rows through LDS.  A lane holds P consecutive
-// points, so a direct store writes one double per lane at a stride of P doubles
-// and a 128-byte line fills only over P store instructions (partly written lines
-// then leave the L2 more than once); staged point-major, consecutive lanes store
-// consecutive positions and every store instruction writes whole lines.  One
-// padding double per P points keeps both LDS passes free of bank conflicts.
-template <int P>
-constexpr int stage_span() { return 64 * P + 64; }
+// ---- one-wave tiles: the computed set packed into as few points per lane as it needs ----
+//
+// A triangle's computed set narrows (and a Diamond's lower half widens) by r
+// points per side per level, so a fixed layout of P0 points per lane leaves half
+// of the lanes idle on average (the idle threads of the paper's Results).  A
+// one-wave tile therefore keeps both rows of the whole tile in LDS and holds in
+// registers only a class layout: the 64 P points [w/2 - 32 P, w/2 + 32 P) centred
+// in the tile, lane g owning P consecutive ones, with P the smallest power of two
+// (at least 2) whose layout holds the level's computed set and its halo,
+// r m + r <= 32 P.  At a change of class the lanes park their rows in LDS and fetch
+// the next layout; positions outside the layout keep their values there (inserted
+// edges not yet reached by a widening set, finished values left behind by a
+// narrowing one).  The computed set then covers about three quarters of the lane
+// slots instead of half.  Row loads and stores go through the same LDS copy,
+// point-major, so every global access instruction moves 64 consecutive doubles.
+//
+// LDS position of tile point x: x + x/16 (one padding double per 16), which keeps
+// the stride-P accesses of every class layout and the point-major passes free of
+// bank conflicts.
+constexpr int wave_span(int P0) { return 68 * P0; }   // w + w/16 doubles per row, w = 64 P0
+__device__ __forceinline__ int lds_pos(int x) { return x + (x >> 4); }
+constexpr int min_class(int P0) { return P0 < 2 ? P0 : 2; }
 
-template <class Sch, int P>
-__device__ __forceinline__ void wave_store(const TileArgs &a, int64_t j, int lane, const double (&r0)[Sch::NV][P],
-                                           const double (&r1)[Sch::NV][P], double *stage)
+template <class Sch, int P, int SPAN>
+__device__ __forceinline__ void fetch_rows(const double *stage, int org, int lane, double (&r0)[Sch::NV][P],
+                                           double (&r1)[Sch::NV][P])
 {
-    constexpr int NV = Sch::NV, SPAN = stage_span<P>();
-    __syncthreads();  // the work-group's previous tile has finished reading the stage
 #pragma unroll
-    for (int v = 0; v < NV; ++v)
+    for (int v = 0; v < Sch::NV; ++v)
 #pragma unroll
         for (int k = 0; k < P; ++k) {
-            stage[(2 * v + 0) * SPAN + lane * (P + 1) + k] = r0[v][k];
-            stage[(2 * v + 1) * SPAN + lane * (P + 1) + k] = r1[v][k];
+            const int i = lds_pos(org + lane * P + k);
+            r0[v][k] = stage[(2 * v + 0) * SPAN + i];
+            r1[v][k] = stage[(2 * v + 1) * SPAN + i];
+        }
+}
+
+template <class Sch, int P, int SPAN>
+__device__ __forceinline__ void park_rows(double *stage, int org, int lane, const double (&r0)[Sch::NV][P],
+                                          const double (&r1)[Sch::NV][P])
+{
+#pragma unroll
+    for (int v = 0; v < Sch::NV; ++v)
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            const int i = lds_pos(org + lane * P + k);
+            stage[(2 * v + 0) * SPAN + i] = r0[v][k];
+            stage[(2 * v + 1) * SPAN + i] = r1[v][k];
         }
     __syncthreads();
-    if (a.kind != PH_DOWN) {
-        double *sa = a.edges + slot_base<Sch>(a, slot_a(a, j));
-        double *sb = a.edges + slot_base<Sch>(a, slot_b(a, j));
-#pragma unroll
-        for (int i = 0; i < P; ++i) {
-            const int x = 64 * i + lane, idx = x + x / P;
-#pragma unroll
-            for (int v = 0; v < NV; ++v)
-                store_edge_point<Sch>(a, sa, sb, v, x, stage[(2 * v + 0) * SPAN + idx],
-                                      stage[(2 * v + 1) * SPAN + idx]);
-        }
+}
+
+// Narrowing levels [s, s_last] (m = mtop - s) from class P downwards.  Class P holds
+// them while m >= 16 P / r (the smaller class's limit plus one); every class starts at
+// a level = 1 modulo its group length (mtop and 16 P / r are multiples of it).
+template <class Sch, int P, int P0, bool WALL>
+__device__ __forceinline__ void wave_narrow(const TileArgs &a, int lane, double *stage, int s, int s_last,
+                                            int mtop, const double (&hl)[Sch::NV][Sch::R],
+                                            const double (&hr)[Sch::NV][Sch::R])
+{
+    constexpr int NV = Sch::NV, R = Sch::R, SPAN = wave_span(P0);
+    const int s_next = P > min_class(P0) ? mtop - 16 * P / R + 1 : s_last + 1;   // first level of P/2
+    const int cap = s_last < s_next - 1 ? s_last : s_next - 1;
+    if (s <= cap) {
+        const int org = (a.w >> 1) - 32 * P;
+        double r0[NV][P], r1[NV][P];
+        fetch_rows<Sch, P, SPAN>(stage, org, lane, r0, r1);
+        run_segment<Sch, P, false, WALL, false, 1>(a, lane, 1, s, cap, mtop, r0, r1, hl, hr, nullptr, org);
+        park_rows<Sch, P, SPAN>(stage, org, lane, r0, r1);
     }
-    int lo, hi;
-    const int top = store_top_level<Sch>(a, lo, hi);
-    if (top < 0) return;
-    const int64_t g0 = tile_start(a, j);
-#pragma unroll
-    for (int i = 0; i < P; ++i) {
-        const int x = 64 * i + lane, idx = x + x / P;
-        if (x >= lo && x < hi) {
-#pragma unroll
-            for (int v = 0; v < NV; ++v)
-                store_top_point<Sch>(a, g0, top, v, x, stage[(2 * v + 0) * SPAN + idx],
-                                     stage[(2 * v + 1) * SPAN + idx]);
+    if constexpr (P > min_class(P0)) {
+        if (s_last >= s_next)
+            wave_narrow<Sch, P / 2, P0, WALL>(a, lane, stage, s > s_next ? s : s_next, s_last, mtop, hl, hr);
+    }
+}
+
+// Widening levels [s, top] (m = s) from class P upwards; class P holds them while
+// r m + r <= 32 P, and the next class starts at m = 32 P / r (= 0 modulo its group
+// length; the smallest class starts at level 1).  The full-width class P0 also runs
+// a Diamond's narrowing levels [top + 1, n_last] before handing over to the classes
+// below it.
+template <class Sch, int P, int P0, bool WALL>
+__device__ __forceinline__ void wave_widen(const TileArgs &a, int lane, double *stage, int s, int top,
+                                           int n_last, const double (&hl)[Sch::NV][Sch::R],
+                                           const double (&hr)[Sch::NV][Sch::R])
+{
+    constexpr int NV = Sch::NV, R = Sch::R, SPAN = wave_span(P0);
+    constexpr int A = P == min_class(P0) ? 1 : 0;
+    const int org = (a.w >> 1) - 32 * P;
+    if constexpr (P < P0) {
+        const int cap = top < 32 * P / R - 1 ? top : 32 * P / R - 1;
+        if (s <= cap) {
+            double r0[NV][P], r1[NV][P];
+            fetch_rows<Sch, P, SPAN>(stage, org, lane, r0, r1);
+            run_segment<Sch, P, false, WALL, true, A>(a, lane, 1, s, cap, 0, r0, r1, hl, hr, nullptr, org);
+            park_rows<Sch, P, SPAN>(stage, org, lane, r0, r1);
+        }
+        if (cap < top) wave_widen<Sch, 2 * P, P0, WALL>(a, lane, stage, cap + 1, top, n_last, hl, hr);
+    } else {
+        double r0[NV][P], r1[NV][P];
+        fetch_rows<Sch, P, SPAN>(stage, org, lane, r0, r1);
+        run_segment<Sch, P, false, WALL, true, A>(a, lane, 1, s, top, 0, r0, r1, hl, hr, nullptr, org);
+        const int mtop = 2 * a.H;
+        const int s_next = P > min_class(P0) ? mtop - 16 * P / R + 1 : n_last + 1;
+        const int cap = n_last < s_next - 1 ? n_last : s_next - 1;
+        if (top + 1 <= cap)
+            run_segment<Sch, P, false, WALL, false, 1>(a, lane, 1, top + 1, cap, mtop, r0, r1, hl, hr, nullptr, org);
+        park_rows<Sch, P, SPAN>(stage, org, lane, r0, r1);
+        if constexpr (P > min_class(P0)) {
+            if (n_last >= s_next) wave_narrow<Sch, P / 2, P0, WALL>(a, lane, stage, s_next, n_last, mtop, hl, hr);
         }
     }
 }
 
-// One tile of one phase: load the two rows, run the phase's levels, store.
-// `stage` (one-wave work-groups only) holds 2 NV stage_span<P>() doubles of LDS.
+// One tile of one phase on a one-wave work-group.  `stage` holds 2 NV wave_span(P0)
+// doubles of LDS: both rows of the tile.
+template <class Sch, int P0>
+__device__ __forceinline__ void wave_tile(const TileArgs &args, int64_t j, int lane, double *stage)
+{
+    constexpr int NV = Sch::NV, R = Sch::R, SPAN = wave_span(P0);
+    TileArgs a = args;
+    a.ends = tile_ends(args, j);
+    const int half = a.w >> 1;
+    double hl[NV][R], hr[NV][R];
+    __syncthreads();   // the work-group's previous tile has finished with the stage
+    if (a.kind == PH_UP) {
+        const int64_t g0 = tile_start(a, j);
+#pragma unroll
+        for (int i = 0; i < P0; ++i) {
+            const int x = 64 * i + lane;
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                stage[(2 * v + 0) * SPAN + lds_pos(x)] = a.state[(int64_t)v * a.n + g0 + x];
+                stage[(2 * v + 1) * SPAN + lds_pos(x)] = 0.0;
+            }
+        }
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+#pragma unroll
+            for (int i = 0; i < R; ++i) { hl[v][i] = 0.0; hr[v][i] = 0.0; }
+    } else {
+        // left half from slot a (an R slot: points [-r, w/2)), right half from slot b
+        // (an L slot: points [w/2, w + r)); the previous triangles' tips beyond the
+        // tile come with them, read once at the widest level
+        const double *sa = a.edges + slot_base<Sch>(a, slot_a(a, j));
+        const double *sb = a.edges + slot_base<Sch>(a, slot_b(a, j));
+#pragma unroll
+        for (int i = 0; i < P0; ++i) {
+            const int x = 64 * i + lane;
+            const double *src = x < half ? sa + x + R : sb + x - half;
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                stage[(2 * v + 0) * SPAN + lds_pos(x)] = src[(v * 2 + 0) * a.E];
+                stage[(2 * v + 1) * SPAN + lds_pos(x)] = src[(v * 2 + 1) * a.E];
+            }
+        }
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+#pragma unroll
+            for (int i = 0; i < R; ++i) {
+                hl[v][i] = sa[(v * 2 + 1) * a.E + i];
+                hr[v][i] = sb[(v * 2 + 1) * a.E + half + i];
+            }
+        }
+        if (a.bc == BC_DIRICHLET && a.offset == 0) {   // the unshifted tiles at the walls
+#pragma unroll
+            for (int v = 0; v < NV; ++v)
+#pragma unroll
+                for (int i = 0; i < R; ++i) {
+                    if (j == 0) hl[v][i] = a.c.ghost_l[v];
+                    if (j == a.K - 1) hr[v][i] = a.c.ghost_r[v];
+                }
+        }
+    }
+    __syncthreads();
+    const int nlev = tile_levels(a);
+    const bool wall = straddles_wall(a, j);
+    if (a.kind == PH_UP) {
+        if (wall) wave_narrow<Sch, P0, P0, true>(a, lane, stage, 1, nlev, a.H, hl, hr);
+        else wave_narrow<Sch, P0, P0, false>(a, lane, stage, 1, nlev, a.H, hl, hr);
+    } else {
+        const int top = a.kind == PH_DOWN ? nlev : a.H;
+        const int n_last = a.kind == PH_DIAMOND ? nlev : 0;
+        if (wall) wave_widen<Sch, min_class(P0), P0, true>(a, lane, stage, 1, top, n_last, hl, hr);
+        else wave_widen<Sch, min_class(P0), P0, false>(a, lane, stage, 1, top, n_last, hl, hr);
+    }
+    // every class parked its rows: the stage holds both final rows of the whole tile
+    if (a.kind != PH_DOWN) {
+        double *sa = a.edges + slot_base<Sch>(a, slot_a(a, j));
+        double *sb = a.edges + slot_base<Sch>(a, slot_b(a, j));
+#pragma unroll
+        for (int i = 0; i < P0; ++i) {
+            const int x = 64 * i + lane;
+#pragma unroll
+            for (int v = 0; v < NV; ++v)
+                store_edge_point<Sch>(a, sa, sb, v, x, stage[(2 * v + 0) * SPAN + lds_pos(x)],
+                                      stage[(2 * v + 1) * SPAN + lds_pos(x)]);
+        }
+    }
+    int lo, hi;
+    const int topl = store_top_level<Sch>(a, lo, hi);
+    if (topl < 0) return;
+    const int64_t g0 = tile_start(a, j);
+#pragma unroll
+    for (int i = 0; i < P0; ++i) {
+        const int x = 64 * i + lane;
+        if (x >= lo && x < hi) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v)
+                store_top_point<Sch>(a, g0, topl, v, x, stage[(2 * v + 0) * SPAN + lds_pos(x)],
+                                     stage[(2 * v + 1) * SPAN + lds_pos(x)]);
+        }
+    }
+}
+
+// One tile of one phase on a multi-wave work-group: load the two rows, run the
+// phase's levels with one barrier and LDS exchange per level, store.
 template <class Sch, int P>
 __device__ __forceinline__ void tile_body(const TileArgs &args, int64_t j, int g, int NW,
-                                          double (*xch)[16][2][Sch::NV][Sch::R], double *stage)
+                                          double (*xch)[16][2][Sch::NV][Sch::R])
 {
     constexpr int NV = Sch::NV, R = Sch::R;
     TileArgs a = args;
     a.ends = tile_ends(args, j);
     double r0[NV][P], r1[NV][P], hl[NV][R], hr[NV][R];
     lane_load<Sch, P>(a, j, g, r0, r1, hl, hr);
-    const bool wall = straddles_wall(a, j);
-    if (NW > 1) {
-        if (wall) run_levels<Sch, P, true, true>(a, g, NW, r0, r1, hl, hr, xch);
-        else run_levels<Sch, P, true, false>(a, g, NW, r0, r1, hl, hr, xch);
-        __syncthreads();  // every wave has read its inputs before any slot is rewritten
-    } else {
-        if (wall) run_levels<Sch, P, false, true>(a, g, NW, r0, r1, hl, hr, xch);
-        else run_levels<Sch, P, false, false>(a, g, NW, r0, r1, hl, hr, xch);
-    }
-    if (stage) wave_store<Sch, P>(a, j, g, r0, r1, stage);
-    else lane_store<Sch, P>(a, j, g, r0, r1);
+    if (straddles_wall(a, j)) run_levels<Sch, P, true, true>(a, g, NW, r0, r1, hl, hr, xch);
+    else run_levels<Sch, P, true, false>(a, g, NW, r0, r1, hl, hr, xch);
+    __syncthreads();  // every wave has read its inputs before any slot is rewritten
+    lane_store<Sch, P>(a, j, g, r0, r1);
 }
 
 // MAXT bounds the work-group size the kernel is compiled for.  MAXT = 64 is the
-// one-wave tile: the multi-wave path (LDS exchange, barriers) is compiled out,
-// the rows are stored through LDS, and the register allocator is not held to a
-// many-wave bound's share of the register file.
+// one-wave tile: the multi-wave path (LDS exchange, barriers) is compiled out and
+// the register allocator is not held to a many-wave bound's share of the register
+// file.
 template <class Sch, int P, int MAXT>
 __global__ __launch_bounds__(MAXT) void swept_tile(TileArgs a)
 {
-    __shared__ double xch[2][16][2][Sch::NV][Sch::R];
-    __shared__ double stage[MAXT == 64 ? 2 * Sch::NV * stage_span<P>() : 1];
-    const int NW = MAXT == 64 ? 1 : (int)(blockDim.x >> 6);
-    tile_body<Sch, P>(a, (int64_t)blockIdx.x, (int)threadIdx.x, NW, xch, MAXT == 64 ? stage : nullptr);
+    if constexpr (MAXT == 64) {
+        __shared__ double stage[2 * Sch::NV * wave_span(P)];
+        wave_tile<Sch, P>(a, (int64_t)blockIdx.x, (int)threadIdx.x, stage);
+    } else {
+        __shared__ double xch[2][16][2][Sch::NV][Sch::R];
+        tile_body<Sch, P>(a, (int64_t)blockIdx.x, (int)threadIdx.x, (int)(blockDim.x >> 6), xch);
+    }
 }
 
 // Batched phase: every work item is (solve, tile) of one of many independent
@@ -411,8 +574,7 @@ __global__ __launch_bounds__(64) void batch_tiles(const SolveDesc *__restrict__ 
                                                   const int2 *__restrict__ items, int64_t nitems,
                                                   int global_phase)
 {
-    __shared__ double xch[2][16][2][Sch::NV][Sch::R];
-    __shared__ double stage[2 * Sch::NV * stage_span<P>()];
+    __shared__ double stage[2 * Sch::NV * wave_span(P)];
     for (int64_t i = blockIdx.x; i < nitems; i += gridDim.x) {
         const int2 it = items[i];
         const SolveDesc &d = desc[it.x];
@@ -430,7 +592,7 @@ __global__ __launch_bounds__(64) void batch_tiles(const SolveDesc *__restrict__ 
         a.ends = 0;
         a.c = d.c;
         phase_at(d.Q, d.rem, d.H, p, a.kind, a.levels, a.offset);
-        tile_body<Sch, P>(a, (int64_t)it.y, (int)threadIdx.x, 1, xch, stage);
+        wave_tile<Sch, P>(a, (int64_t)it.y, (int)threadIdx.x, stage);
     }
 }
 

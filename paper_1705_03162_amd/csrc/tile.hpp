@@ -1,7 +1,7 @@
 // Geometry of one swept tile: which points a lane owns, where its two working
 // rows come from and go to, and which points each level computes.
 //
-// Swept rule on a 1D grid (Sec. 3.2, Fig. 1 and 2; Sec. 3.3 for two sub-steps):
+// Swept rule on a 1D grid (Sec. 4.2, Fig. 1 and 2; Sec. 4.3 for two sub-steps):
 // a node of w points advances every level its domain of dependence allows.  A
 // stencil of radius r shrinks the computable set by r per side per level, so an
 // Up triangle computes levels 1..H-1 on [r s, w - r s) with H = w / (2 r).  The
@@ -9,7 +9,7 @@
 // by w/2, fills the gap between two triangles (a Diamond: widening for H levels,
 // narrowing for H-1 more), and a final Down triangle completes a full level.
 //
-// Working array (Sec. 3.2): two rows, row 0 for even and row 1 for odd levels,
+// Working array (Sec. 4.2): two rows, row 0 for even and row 1 for odd levels,
 // overwritten in place; the edges left behind in the rows are exactly the values
 // the neighbour needs.  Here the two rows of a tile live in registers: lane g of
 // the work-group owns the P consecutive points [g P, g P + P) of both rows.
@@ -22,7 +22,7 @@
 // j reads slot a = 2j + o (an R slot: its points [-r, w/2)) and slot
 // b = 2j + o + 1 (an L slot: its points [w/2, w + r)), and writes its own L and R
 // slots back into a and b: each slot is read and rewritten by exactly one tile
-// per launch (the L/R swap of Sec. 3.2).
+// per launch (the L/R swap of Sec. 4.2).
 //
 // Relative levels start at an even absolute level in every phase (H is even), so
 // odd relative levels are the odd absolute levels: predictors for RK2 schemes.
@@ -85,7 +85,7 @@ SW_HD int64_t slot_base(const TileArgs &a, int64_t s) { return s * (int64_t)Sch:
 
 // Phase p of a solve with Q full phases of H levels and a remainder of rem
 // levels: Up(H), Diamond x (Q-1) at offsets 1, 0, 1, ..., Down(H) at offset
-// Q mod 2, then Up(rem), Down(rem) at offsets 0, 1 (Sec. 3.2's zig-zag).
+// Q mod 2, then Up(rem), Down(rem) at offsets 0, 1 (Sec. 4.2's zig-zag).
 SW_HD int phase_count(int64_t Q, int64_t rem) { return (int)((Q >= 1 ? Q + 1 : 0) + (rem > 0 ? 2 : 0)); }
 SW_HD void phase_at(int64_t Q, int64_t rem, int H, int64_t p, int32_t &kind, int32_t &levels,
                     int32_t &offset)

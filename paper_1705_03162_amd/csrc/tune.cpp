@@ -17,6 +17,7 @@ namespace {
 
 std::once_flag g_once;
 std::map<std::pair<int, int>, std::pair<int, int>> g_table;
+std::map<std::pair<int, int>, int> g_classic;
 
 std::string table_path()
 {
@@ -39,7 +40,9 @@ void load()
     while (std::fgets(line, sizeof line, f)) {
         if (line[0] == '#') continue;
         int scheme, lg, width, threads;
-        if (std::sscanf(line, "%d %d %d %d", &scheme, &lg, &width, &threads) == 4)
+        if (std::sscanf(line, "classic %d %d %d", &scheme, &lg, &threads) == 3)
+            g_classic[{scheme, lg}] = threads;
+        else if (std::sscanf(line, "%d %d %d %d", &scheme, &lg, &width, &threads) == 4)
             g_table[{scheme, lg}] = {width, threads};
     }
     std::fclose(f);
@@ -47,11 +50,29 @@ void load()
 
 }  // namespace
 
+static int size_class(int64_t n)
+{
+    int lg = 0;
+    while (lg < 62 && ((int64_t)1 << (lg + 1)) <= n) ++lg;
+    return lg;
+}
+
+bool tuned_classic_threads(const sw_problem &p, int *threads)
+{
+    std::call_once(g_once, load);
+    const int lg = size_class(p.n);
+    auto it = g_classic.end();
+    for (int c = lg; c >= 0 && it == g_classic.end(); --c) it = g_classic.find({p.scheme, c});
+    for (int c = lg + 1; c <= 62 && it == g_classic.end(); ++c) it = g_classic.find({p.scheme, c});
+    if (it == g_classic.end() || !legal_threads(it->second)) return false;
+    *threads = it->second;
+    return true;
+}
+
 bool tuned_shape(const sw_problem &p, int *width, int *threads)
 {
     std::call_once(g_once, load);
-    int lg = 0;
-    while (lg < 62 && ((int64_t)1 << (lg + 1)) <= p.n) ++lg;
+    const int lg = size_class(p.n);
     // the measured size class of n, else the nearest smaller one (beyond the largest
     // measured class the device is saturated), else the nearest larger one
     auto it = g_table.end();

@@ -1,13 +1,14 @@
-"""Autotuner for the swept tile shape.
+"""Autotuner for the swept tile shape and the classic work-group size.
 
 For each (scheme, floor(log2 n)) it times swept solves over every legal
-(width, threads) pair that divides n and writes the fastest to
-tune_gfx950.txt next to libswept.so; swept_plan() reads that table whenever
-the caller does not fix a shape.  The choice never changes results: the
-decomposition is bitwise identical for every shape (the GPU tests check it).
-The paper likewise reports the best block size per grid size (Sec. 5).
+(width, threads) pair that divides n, and classic solves over work-group sizes
+64..1024, and writes the fastest to tune_gfx950.txt next to libswept.so;
+swept_plan() reads that table whenever the caller does not fix a shape.  The
+choice never changes results: the decomposition is bitwise identical for every
+shape (the GPU tests check it).  The paper likewise takes the best time over
+block sizes per grid size (Sec. 4.1, experimental method; Sec. 6).
 
-    python -m paper_1705_03162_amd.tune [--schemes heat,ks,euler] [--log2n 12-20]
+    python -m paper_1705_03162_amd.tune [--schemes heat,ks,euler] [--log2n 12-20] [--what swept,classic]
 """
 from __future__ import annotations
 
@@ -67,6 +68,75 @@ def time_shape(sw, torch, prob, ic, width, threads, reps):
     return best
 
 
+CLASSIC_THREADS = (64, 128, 256, 512, 1024)
+
+
+def read_table(table: str = TABLE):
+    """(swept rows {(scheme, lg): line}, classic rows {(scheme, lg): line}) of a table file."""
+    swept, classic = {}, {}
+    if os.path.exists(table):
+        with open(table) as f:
+            for line in f:
+                parts = line.split()
+                if not parts or parts[0].startswith("#"):
+                    continue
+                if parts[0] == "classic" and len(parts) >= 4:
+                    classic[(int(parts[1]), int(parts[2]))] = line.rstrip("\n")
+                elif len(parts) >= 4:
+                    swept[(int(parts[0]), int(parts[1]))] = line.rstrip("\n")
+    return swept, classic
+
+
+def write_table(swept, classic, table: str = TABLE):
+    with open(table + ".tmp", "w") as f:
+        f.write("# scheme log2n width threads  (point-updates/s, steps timed)\n")
+        for k in sorted(swept):
+            f.write(swept[k] + "\n")
+        f.write("# classic scheme log2n threads  (point-updates/s, steps timed)\n")
+        for k in sorted(classic):
+            f.write(classic[k] + "\n")
+    os.replace(table + ".tmp", table)
+
+
+def time_classic(sw, torch, prob, ic, threads, reps):
+    with sw.Plan(prob, classic_threads=threads) as plan:
+        x0 = torch.tensor(ic, dtype=torch.float64, device="cuda")
+        x = x0.clone()
+        plan.classic(x)              # warm: graph capture
+        best = float("inf")
+        for _ in range(reps):
+            x.copy_(x0)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            plan.classic(x)
+            torch.cuda.synchronize()
+            best = min(best, time.perf_counter() - t0)
+    return best
+
+
+def tune_classic(schemes=(0, 1, 2), log2ns=range(12, 21), target_s: float = 0.02, reps: int = 3,
+                 table: str = TABLE, log=print):
+    """Best classic work-group size per (scheme, size class), merged into the table."""
+    import torch
+
+    import paper_1705_03162_amd as sw
+    swept, classic = read_table(table)
+    for scheme in schemes:
+        for lg in log2ns:
+            n = 1 << lg
+            prob, ic = _problem(scheme, lg, 256)
+            t = time_classic(sw, torch, prob, ic, 256, reps=1)
+            steps = int(min(20_000, max(256, 256 * target_s / max(t, 1e-6))))
+            prob, ic = _problem(scheme, lg, steps)
+            results = sorted((time_classic(sw, torch, prob, ic, T, reps), T) for T in CLASSIC_THREADS)
+            t, T = results[0]
+            rate = n * steps / t
+            log(f"classic scheme={scheme} log2n={lg} steps={steps} best T={T} {rate:.3e} pt-upd/s; "
+                + ", ".join(f"T={tt}: {n * steps / x:.3e}" for x, tt in sorted(results, key=lambda r: r[1])))
+            classic[(scheme, lg)] = f"classic {scheme} {lg} {T}  # {rate:.4e} {steps}"
+    write_table(swept, classic, table)
+
+
 def tune(schemes=(0, 1, 2), log2ns=range(12, 21), target_s: float = 0.02, reps: int = 3,
          table: str = TABLE, log=print, verbose: bool = False):
     import torch
@@ -99,11 +169,10 @@ def tune(schemes=(0, 1, 2), log2ns=range(12, 21), target_s: float = 0.02, reps: 
             log(f"scheme={scheme} log2n={lg} steps={steps} best w={w} T={th} "
                 f"{rate:.3e} pt-upd/s; worst {n * steps / results[-1][0]:.3e}")
             rows.append((scheme, lg, w, th, rate, steps))
-    with open(table + ".tmp", "w") as f:
-        f.write("# scheme log2n width threads  (point-updates/s, steps timed)\n")
-        for scheme, lg, w, th, rate, steps in rows:
-            f.write(f"{scheme} {lg} {w} {th}  # {rate:.4e} {steps}\n")
-    os.replace(table + ".tmp", table)
+    swept, classic = read_table(table)
+    for scheme, lg, w, th, rate, steps in rows:
+        swept[(scheme, lg)] = f"{scheme} {lg} {w} {th}  # {rate:.4e} {steps}"
+    write_table(swept, classic, table)
     return rows
 
 
@@ -114,13 +183,19 @@ def main():
     ap.add_argument("--table", default=TABLE)
     ap.add_argument("--target-ms", type=float, default=20.0)
     ap.add_argument("--verbose", action="store_true", help="log every shape timed")
+    ap.add_argument("--what", default="swept,classic", help="swept, classic or both")
     args = ap.parse_args()
     names = {"heat": 0, "ks": 1, "euler": 2}
     schemes = [names[s] for s in args.schemes.split(",")]
     a, b = (int(x) for x in args.log2n.split("-"))
     sys.path.insert(0, os.path.dirname(HERE))
-    tune(schemes, range(a, b + 1), target_s=args.target_ms / 1000.0, table=args.table,
-         log=lambda m: print(m, flush=True), verbose=args.verbose)
+    what = args.what.split(",")
+    log = lambda m: print(m, flush=True)  # noqa: E731
+    if "swept" in what:
+        tune(schemes, range(a, b + 1), target_s=args.target_ms / 1000.0, table=args.table, log=log,
+             verbose=args.verbose)
+    if "classic" in what:
+        tune_classic(schemes, range(a, b + 1), target_s=args.target_ms / 1000.0, table=args.table, log=log)
 
 
 if __name__ == "__main__":

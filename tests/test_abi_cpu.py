@@ -88,7 +88,7 @@ def _phase_levels(width, radius):
 
 
 def test_paper_geometry_pins():
-    """Printed geometry of Sec. 3.2 and Sec. 5 follows from H = w/(2r) and two rows of
+    """Printed geometry of Sec. 4.2 and Sec. 6 follows from H = w/(2r) and two rows of
     w + k - 1 values (k = 2r + 1)."""
     n = 512
     assert sum(2 * j for j in range(1, n // 2 + 1)) == GOLDEN["full_triangle_values_n512_radius1"]["value"]
@@ -231,3 +231,4 @@ def test_binding_rejects_bad_state_before_the_library(lib):
             plan.swept(torch.zeros(1024, dtype=torch.float64))          # host tensor
         with pytest.raises(ValueError):
             plan.classic(torch.zeros(1024, dtype=torch.float32))        # wrong dtype
+

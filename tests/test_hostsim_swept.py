@@ -146,7 +146,7 @@ def test_phase_sequence_shape(hostsim):
     assert ph[312] == (2, 32, 0)          # Down after 311 diamonds: 312 shifts, offset 0
     assert ph[313:] == [(0, 16, 0), (2, 16, 1)]
     assert len(ph) == 315
-    # KS, w=1024: H=256 levels = 128 steps per phase (Sec. 3.3: two sub-steps per step)
+    # KS, w=1024: H=256 levels = 128 steps per phase (Sec. 4.3: two sub-steps per step)
     ph = phases(hostsim, W.ks_problem(1 << 20, 50_000), 1024, 64)
     # 100,000 levels = 390 phases of 256 + 160: Up, 389 Diamonds, Down, Up(160), Down(160)
     assert ph[0] == (0, 256, 0) and len(ph) == 393 and ph[-2:] == [(0, 160, 0), (2, 160, 1)]

@@ -7,7 +7,7 @@ receive the very same arrays built here, so transcendental-function differences
 between libraries can never leak into a parity comparison.
 
 The paper uses no dataset: every workload is a synthetic initial-value problem
-(heat equation, Kuramoto-Sivashinsky equation, Sod shock tube; Sec. 4.2 and
+(heat equation, Kuramoto-Sivashinsky equation, Sod shock tube; Sec. 5.2 and
 Appendices B-D).  The concrete recipes below (mode counts, seeds, step sizes)
 are this project's stand-ins for the paper's workloads.
 """
