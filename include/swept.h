@@ -153,6 +153,31 @@ void swept_plan_destroy(sw_plan *plan);
 int swept_profile_phase(sw_plan *plan, double *d_state, int32_t kind, int32_t reps,
                         void *hip_stream, double *avg_us);
 
+/* ---- allocation-free solve --------------------------------------------- */
+/* For callers that cannot allocate device memory: code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc.  The same swept solve as
+ * swept_solve on a plan of this problem and tile shape (bit-identical results),
+ * but its edge slots live in a static device array of SW_NOALLOC_SCRATCH_BYTES
+ * that the library holds on every device it runs on until the process ends, and
+ * its phases are enqueued one by one on hip_stream (no graph is built).  The call
+ * allocates nothing: no hipMalloc, hipFree or allocating library routine (the
+ * first call on a device only resolves that device's copy of the array).
+ *  - problem, tuning: as for swept_plan (tuning may be NULL; its only accepted
+ *    flag is SW_TUNE_NO_GRAPH).  d_state: caller-owned device state, as for
+ *    swept_solve.  Asynchronous on hip_stream.
+ *  - The edge scratch needs nvars * (2 n + 4 K r) doubles (K = n / width); a
+ *    problem needing more than SW_NOALLOC_SCRATCH_BYTES is rejected with
+ *    SW_EINVAL before anything is enqueued (32 MiB: heat and KS up to n = 2^20,
+ *    Euler up to n = 2^19).  SW_EUNSUPPORTED if no legal width divides n.
+ *  - Every call on one device shares that device's array and leaves its last
+ *    contents behind (nothing in it has to start at zero: each solve's first
+ *    phase writes every slot before any is read).  Calls that overlap on one
+ *    device -- on different streams, or from different threads -- race on it and
+ *    must be serialised by the caller. */
+#define SW_NOALLOC_SCRATCH_BYTES (32ll << 20)
+int swept_solve_noalloc(const sw_problem *problem, const sw_tuning *tuning, double *d_state,
+                        void *hip_stream);
+
 /* ---- batched / served solves ------------------------------------------- */
 /* Many independent solves share launches.  The paper runs one solve at a time;
  * batching many solves of uneven n into shared phase launches, and serving

@@ -18,7 +18,7 @@ from . import _native as N
 from ._native import (SW_DIRICHLET, SW_EULER, SW_HEAT, SW_KS, SW_PERIODIC, SW_REFLECTIVE, SW_TUNE_CHECK_NAN,
                       SW_TUNE_NO_GRAPH, SweptError, problem_struct)
 
-__all__ = ["Plan", "Batch", "swept_plan", "swept_solve", "classic_solve", "SweptError",
+__all__ = ["Plan", "Batch", "swept_plan", "swept_solve", "classic_solve", "swept_solve_noalloc", "SweptError",
            "SW_HEAT", "SW_KS", "SW_EULER", "SW_PERIODIC", "SW_DIRICHLET", "SW_REFLECTIVE",
            "SW_TUNE_NO_GRAPH", "SW_TUNE_CHECK_NAN"]
 
@@ -107,6 +107,19 @@ def swept_plan(problem, width: int = 0, threads: int = 0, flags: int = 0, limite
 def swept_solve(plan: Plan, state, stream=None):
     return plan.swept(state, stream)
 
+
+def swept_solve_noalloc(problem, state, width: int = 0, threads: int = 0, limiter: int = 0,
+                        stream=None):
+    """The allocation-free swept solve (edges in the library's static device scratch)."""
+    p = problem_struct(problem, limiter)
+    tun = N.SwTuning(int(width), int(threads), 0)
+    N.check(N.lib().swept_solve_noalloc(ctypes.byref(p), ctypes.byref(tun), _state_ptr(state, problem),
+                                        _stream_handle(stream)), "swept_solve_noalloc")
+    return state
+
+
+def classic_solve(plan: Plan, state, stream=None):
+    return plan.classic(state, stream)
 
 
 class Batch:

@@ -19,6 +19,7 @@ SW_HEAT, SW_KS, SW_EULER = 0, 1, 2
 SW_PERIODIC, SW_DIRICHLET, SW_REFLECTIVE = 0, 1, 2
 SW_PROBLEM_LIMITER_RECIPROCAL = 1
 SW_TUNE_NO_GRAPH, SW_TUNE_CHECK_NAN = 1, 2
+SW_NOALLOC_SCRATCH_BYTES = 32 << 20
 SW_TICKET_QUEUED, SW_TICKET_RUNNING, SW_TICKET_DONE, SW_TICKET_FAILED, SW_TICKET_CANCELLED = range(5)
 
 
@@ -97,6 +98,7 @@ SIGNATURES = {
     "swept_plan_destroy": (None, [_VP]),
     "swept_profile_phase": (ctypes.c_int, [_VP, _VP, ctypes.c_int32, ctypes.c_int32, _VP,
                                            ctypes.POINTER(ctypes.c_double)]),
+    "swept_solve_noalloc": (ctypes.c_int, [ctypes.POINTER(SwProblem), ctypes.POINTER(SwTuning), _VP, _VP]),
     "batch_create": (ctypes.c_int, [ctypes.POINTER(SwBatchConfig), ctypes.POINTER(_VP)]),
     "batch_submit": (ctypes.c_int, [_VP, ctypes.POINTER(SwProblem), _VP,
                                     ctypes.POINTER(ctypes.c_uint64)]),

@@ -232,3 +232,18 @@ def test_binding_rejects_bad_state_before_the_library(lib):
         with pytest.raises(ValueError):
             plan.classic(torch.zeros(1024, dtype=torch.float32))        # wrong dtype
 
+
+def test_noalloc_rejects_before_touching_the_device(lib):
+    """The allocation-free solve checks its static scratch limit (32 MiB of edges)
+    and its flags before it looks at the state pointer or the device."""
+    big = N.problem_struct(W.sod_problem(1 << 20, 10))     # Euler at 2^20: ~50 MB of edges
+    rc = lib.swept_solve_noalloc(ctypes.byref(big), None, None, None)
+    assert rc == N.SW_EINVAL
+    assert b"static scratch" in lib.sw_last_error()
+    ok = N.problem_struct(W.ks_problem(1 << 20, 10))      # KS at 2^20 fits (~16.8 MB)
+    t = N.SwTuning(1024, 64, N.SW_TUNE_CHECK_NAN)
+    assert lib.swept_solve_noalloc(ctypes.byref(ok), ctypes.byref(t), None, None) == N.SW_EINVAL
+    assert b"flags" in lib.sw_last_error()
+    t = N.SwTuning(1024, 64, 0)
+    assert lib.swept_solve_noalloc(ctypes.byref(ok), ctypes.byref(t), None, None) == N.SW_EINVAL
+    assert b"NULL" in lib.sw_last_error()                  # got past the size check to the state
