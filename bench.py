@@ -321,6 +321,33 @@ def suite_sweep(schemes, log2ns, max_steps):
                 f"stream {rst:.3e} e2e swept {upd / e2e_s:.3e}")
 
 
+def suite_hybrid(log2ns=range(12, 21), max_steps=20_000):
+    """Hybrid variant (the host CPU computes the straddling tile of every shifted phase)
+    against the all-GPU swept solve on the same tile shape: the paper's insulated heat
+    case (50,000 steps) and the Sod tube (to t = 0.2, at most max_steps steps), one JSON
+    line per (scheme, N), median of 3 timed solves each; results compared bit for bit."""
+    import torch
+    import paper_1705_03162_amd as sw
+    for scheme in (W.HEAT, W.EULER):
+        for lg in log2ns:
+            n = 1 << lg
+            if scheme == W.HEAT:
+                prob, ic = W.heat_problem(n, 50_000, bc=W.REFLECTIVE), W.fourier_ic(n, seed=2 + lg)
+            else:
+                prob, ic = W.cfg_sod(lg)
+                prob = prob.with_steps(min(prob.nsteps, max_steps))
+            rs, ts, info, xs = rate_of(sw, torch, prob, ic, "swept", reps=3, stat=np.median)
+            w, t = info["width"], info["threads"]
+            rh, th, _, xh = rate_of(sw, torch, prob, ic, "swept", flags=sw.SW_TUNE_HYBRID, reps=3,
+                                    width=w, threads=t, stat=np.median)
+            line = {"suite": "hybrid", "scheme": W.SCHEME_NAMES[scheme], "bc": prob.bc, "n": n,
+                    "steps": prob.nsteps, "width": w, "threads": t, "shared": rs, "hybrid": rh,
+                    "hybrid_over_shared": rh / rs, "shared_ms": ts * 1e3, "hybrid_ms": th * 1e3,
+                    "bitwise_equal": bool(torch.equal(xs, xh))}
+            print(json.dumps(line), flush=True)
+            log(f"hybrid {W.SCHEME_NAMES[scheme]} 2^{lg}: shared {rs:.3e} hybrid {rh:.3e} ({rh / rs:.2f}x)")
+
+
 def suite_euler_full(log2n=20):
     """Sod at N = 2^20 for the whole run to t = 0.2 (about 1.15M steps), swept and
     classic: times, and whether the two final states are bit-identical."""
@@ -562,7 +589,7 @@ def main():
     ap.add_argument("--profile-reps", type=int, default=30)
     ap.add_argument("--suite", default="main",
                     choices=["main", "sweep", "euler", "euler-full", "ensemble", "serve", "kernel",
-                             "classic-kernel", "anchors", "oracle"],
+                             "classic-kernel", "anchors", "oracle", "hybrid"],
                     help="main: the one-line benchmark; sweep/euler: per-N swept vs classic lines; "
                          "anchors: out-of-cache sizes and a copy; serve: configured and sustainable "
                          "serving; oracle: CPU oracle on all cores and one; kernel, classic-kernel: counter runs")
@@ -623,6 +650,9 @@ def main():
         return
     if args.suite == "euler-full":
         suite_euler_full()
+        return
+    if args.suite == "hybrid":
+        suite_hybrid(max_steps=args.max_steps)
         return
     if args.suite == "anchors":
         suite_anchors()

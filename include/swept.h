@@ -93,6 +93,13 @@ typedef struct {
  * default choice (classic default 256). */
 #define SW_TUNE_NO_GRAPH  1   /* enqueue kernels one by one instead of replaying a HIP graph */
 #define SW_TUNE_CHECK_NAN 2   /* after a solve, synchronise and report SW_ENAN on non-finite output */
+#define SW_TUNE_HYBRID    4   /* Hybrid variant (Sec. 5.1): for Dirichlet and reflective problems,
+                                 the host CPU computes the tile that straddles the domain boundary
+                                 in every shifted phase while the GPU computes the others; its two
+                                 edge slots travel through pinned host memory.  Bit-identical
+                                 results; phases are enqueued one by one (no graph), and a solve
+                                 first waits on the host for the plan's previous solve.  No
+                                 effect for periodic problems. */
 typedef struct {
     int32_t width;
     int32_t threads;

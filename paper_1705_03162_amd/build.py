@@ -21,7 +21,7 @@ LIB = os.path.join(HERE, "libswept.so")
 ARCH = os.environ.get("SWEPT_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["tiles_euler.hip", "tiles_ks.hip", "tiles_heat.hip", "kernels.hip", "api.hip", "batch.hip", "noalloc.hip",
-           "tune.cpp"]
+           "tune.cpp", "hybrid.cpp"]
 CXXFLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", "-fno-fast-math",
     "-Wall", "-Wno-unused-function",

@@ -61,6 +61,26 @@ constexpr size_t kMaxGraphPhases = 4096;   // larger launch lists are replayed i
 constexpr int64_t kDiamondChunk = 2048;    // diamonds per replayed chunk (even: offsets 1,0,...)
 constexpr int64_t kClassicChunkSteps = 256;  // timesteps per replayed classic chunk (even)
 
+bool uses_hybrid(const sw_plan *p)
+{
+    return (p->tflags & SW_TUNE_HYBRID) && p->geom.swept_ok && p->geom.bc != SW_PERIODIC;
+}
+
+// Pinned doubles for the straddling tile: its two slots and one top level.
+size_t hybrid_doubles(const Geom &g) { return (size_t)g.nv * (2 * 2 * (size_t)g.E + (size_t)g.w); }
+
+void release_hybrid(sw_plan *p)
+{
+    if (p->hyb_done) (void)hipEventDestroy(p->hyb_done);
+    if (p->hyb_ready) (void)hipEventDestroy(p->hyb_ready);
+    if (p->hyb_stream) (void)hipStreamDestroy(p->hyb_stream);
+    if (p->h_hybrid) (void)hipHostFree(p->h_hybrid);
+    p->hyb_done = p->hyb_ready = nullptr;
+    p->hyb_stream = nullptr;
+    p->h_hybrid = nullptr;
+    p->hyb_tiles.clear();
+}
+
 int ensure_device(sw_plan *p)
 {
     if (p->device >= 0) return SW_OK;
@@ -76,6 +96,7 @@ int ensure_device(sw_plan *p)
         (void)hipFree(p->d_flag);
         (void)hipFree(p->d_tmp);
         (void)hipFree(p->d_edges);
+        release_hybrid(p);
         p->done = nullptr;
         p->cap = nullptr;
         p->d_flag = nullptr;
@@ -92,6 +113,15 @@ int ensure_device(sw_plan *p)
         return undo(SW_EDEVICE, "capture stream creation failed");
     if (hipEventCreateWithFlags(&p->done, hipEventDisableTiming) != hipSuccess)
         return undo(SW_EDEVICE, "event creation failed");
+    if (uses_hybrid(p)) {
+        if (hipHostMalloc((void **)&p->h_hybrid, hybrid_doubles(g) * sizeof(double), 0) != hipSuccess)
+            return undo(SW_ENOMEM, "pinned host buffer allocation failed");
+        if (hipStreamCreateWithFlags(&p->hyb_stream, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&p->hyb_ready, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&p->hyb_done, hipEventDisableTiming) != hipSuccess)
+            return undo(SW_EDEVICE, "hybrid stream or event creation failed");
+        p->hyb_tiles.assign(p->phases.size(), HybridTile{});
+    }
     p->device = dev;
     return SW_OK;
 }
@@ -130,9 +160,72 @@ void drop_swept_graphs(sw_plan *p)
     p->swept_state = nullptr;
 }
 
+void hybrid_callback(void *ud) { hybrid_tile_host(*static_cast<HybridTile *>(ud)); }
+
+// Hybrid variant: every shifted phase runs tiles 0 .. K-2 on the GPU while the host
+// computes the straddling tile K-1 (slots 2K-1 and 0) on the plan's copy stream.
+int run_hybrid(sw_plan *p, double *state, hipStream_t st)
+{
+    const Geom &g = p->geom;
+    const size_t slot_doubles = (size_t)g.nv * 2 * g.E;
+    double *ha = p->h_hybrid, *hb = ha + slot_doubles, *htop = hb + slot_doubles;
+    hipStream_t cs = p->hyb_stream;
+    const int half = g.w / 2;
+    for (size_t i = 0; i < p->phases.size(); ++i) {
+        const Phase &ph = p->phases[i];
+        const TileArgs a = make_tile_args(g, p->consts, ph, state, p->d_edges);
+        if (ph.offset == 0) {
+            hipError_t e = launch_swept_phase(g.scheme, g.P, g.threads, a, st);
+            if (e != hipSuccess) return hip_fail(e, "swept kernel launch");
+            continue;
+        }
+        HIP_TRY(hipEventRecord(p->hyb_ready, st));   // the phase's inputs are complete
+        hipError_t e = launch_swept_phase(g.scheme, g.P, g.threads, a, st, g.K - 1);
+        if (e != hipSuccess) return hip_fail(e, "swept kernel launch");
+        double *da = p->d_edges + (size_t)(2 * g.K - 1) * slot_doubles, *db = p->d_edges;
+        HIP_TRY(hipStreamWaitEvent(cs, p->hyb_ready, 0));
+        HIP_TRY(hipMemcpyAsync(ha, da, slot_doubles * sizeof(double), hipMemcpyDeviceToHost, cs));
+        HIP_TRY(hipMemcpyAsync(hb, db, slot_doubles * sizeof(double), hipMemcpyDeviceToHost, cs));
+        HybridTile &ht = p->hyb_tiles[i];
+        ht.a = a;
+        ht.scheme = g.scheme;
+        ht.slot_a = ha;
+        ht.slot_b = hb;
+        ht.top = htop;
+        HIP_TRY(hipLaunchHostFunc(cs, hybrid_callback, &ht));
+        if (ph.kind != PH_DOWN) {
+            HIP_TRY(hipMemcpyAsync(da, ha, slot_doubles * sizeof(double), hipMemcpyHostToDevice, cs));
+            HIP_TRY(hipMemcpyAsync(db, hb, slot_doubles * sizeof(double), hipMemcpyHostToDevice, cs));
+        } else {
+            // the top level's points [lo, hi): the tile's left half is the domain's last w/2
+            // points, its right half the first w/2
+            const int lo = half - g.r * ph.levels, hi = half + g.r * ph.levels;
+            for (int v = 0; v < g.nv; ++v) {
+                const double *src = htop + (size_t)v * g.w;
+                double *dst = state + (size_t)v * g.n;
+                const int l1 = lo, h1 = hi < half ? hi : half, l2 = lo > half ? lo : half, h2 = hi;
+                if (h1 > l1)
+                    HIP_TRY(hipMemcpyAsync(dst + g.n - half + l1, src + l1, (size_t)(h1 - l1) * sizeof(double),
+                                           hipMemcpyHostToDevice, cs));
+                if (h2 > l2)
+                    HIP_TRY(hipMemcpyAsync(dst + (l2 - half), src + l2, (size_t)(h2 - l2) * sizeof(double),
+                                           hipMemcpyHostToDevice, cs));
+            }
+        }
+        HIP_TRY(hipEventRecord(p->hyb_done, cs));
+        HIP_TRY(hipStreamWaitEvent(st, p->hyb_done, 0));   // the next phase reads the tile's output
+    }
+    return SW_OK;
+}
+
 int run_swept(sw_plan *p, double *state, hipStream_t st)
 {
     const size_t n = p->phases.size();
+    if (uses_hybrid(p)) {
+        // the previous solve's host callbacks read the per-phase records rewritten here
+        HIP_TRY(hipEventSynchronize(p->done));
+        return run_hybrid(p, state, st);
+    }
     if (p->tflags & SW_TUNE_NO_GRAPH) return enqueue_phases(p, state, 0, n, st);
     if (p->swept_state != state) {
         drop_swept_graphs(p);
@@ -278,6 +371,10 @@ int swept_plan(const sw_problem *problem, const sw_tuning *tuning, sw_plan **out
     p->consts = make_consts(*problem);
     if (g.swept_ok) p->phases = build_phases(g);
     p->tflags = tuning ? tuning->flags : 0;
+    if (p->tflags & ~(SW_TUNE_NO_GRAPH | SW_TUNE_CHECK_NAN | SW_TUNE_HYBRID)) {
+        delete p;
+        return fail(SW_EINVAL, "unknown tuning flags");
+    }
     *out = p;
     return SW_OK;
 }
@@ -363,11 +460,13 @@ void swept_plan_destroy(sw_plan *p)
             (void)hipEventSynchronize(p->done);
             drop_swept_graphs(p);
             if (p->classic_exec) (void)hipGraphExecDestroy(p->classic_exec);
+            if (p->hyb_stream) (void)hipStreamSynchronize(p->hyb_stream);
             (void)hipFree(p->d_edges);
             (void)hipFree(p->d_tmp);
             (void)hipFree(p->d_flag);
             (void)hipEventDestroy(p->done);
             (void)hipStreamDestroy(p->cap);
+            release_hybrid(p);
         }
     }
     delete p;

@@ -7,6 +7,7 @@
 #include <string>
 #include <vector>
 
+#include "hybrid.hpp"
 #include "plan_core.hpp"
 #include "swept.h"
 
@@ -28,6 +29,13 @@ struct sw_plan {
     size_t tail_first = 0;
     hipGraphExec_t classic_exec = nullptr;
     const double *classic_state = nullptr;
+    // Hybrid variant (SW_TUNE_HYBRID): pinned host copies of the straddling tile (slot a,
+    // slot b, top level), the stream that moves them and runs the host computation, and
+    // one host-tile record per phase (read by the host callbacks)
+    double *h_hybrid = nullptr;
+    hipStream_t hyb_stream = nullptr;
+    hipEvent_t hyb_ready = nullptr, hyb_done = nullptr;
+    std::vector<sw::HybridTile> hyb_tiles;
     std::mutex mu;
 };
 

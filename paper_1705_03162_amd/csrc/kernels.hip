@@ -5,6 +5,8 @@
 // instantiated per scheme in tiles_heat.hip, tiles_ks.hip and tiles_euler.hip.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "kernels.hpp"
 
 namespace sw {
@@ -56,6 +58,12 @@ __global__ void advance_phases(SolveDesc *desc, int64_t n)
     if (i < n && desc[i].phase < desc[i].nphases) desc[i].phase += 1;
 }
 
+__global__ void zero_words(uint32_t *p, int64_t count)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0u;
+}
+
 __global__ void stamp_kernel(uint64_t *stamps, int idx)
 {
     if (threadIdx.x == 0) stamps[idx] = wall_clock64();
@@ -71,12 +79,13 @@ __global__ void nonfinite_scan(const double *x, int64_t count, int *flag)
 
 }  // namespace
 
-hipError_t launch_swept_phase(int scheme, int P, int threads, const TileArgs &a, hipStream_t st)
+hipError_t launch_swept_phase(int scheme, int P, int threads, const TileArgs &a, hipStream_t st, int64_t tiles)
 {
-    if (a.K <= 0) return hipSuccess;
-    if (scheme == 0) return swept_phase_for<Heat>(P, threads, a, st);
-    if (scheme == 1) return swept_phase_for<KS>(P, threads, a, st);
-    return swept_phase_for<Euler>(P, threads, a, st);
+    if (tiles < 0 || tiles > a.K) tiles = a.K;
+    if (tiles <= 0) return hipSuccess;
+    if (scheme == 0) return swept_phase_for<Heat>(P, threads, a, st, tiles);
+    if (scheme == 1) return swept_phase_for<KS>(P, threads, a, st, tiles);
+    return swept_phase_for<Euler>(P, threads, a, st, tiles);
 }
 
 template <class Sch>
@@ -114,6 +123,28 @@ int batch_blocks_per_cu(int scheme, int P)
     if (scheme == 0) return batch_blocks_for<Heat>(P);
     if (scheme == 1) return batch_blocks_for<KS>(P);
     return batch_blocks_for<Euler>(P);
+}
+
+hipError_t launch_persistent_batch(int scheme, int P, const PersistArgs &q, int grid, hipStream_t st)
+{
+    if (scheme == 0) return persistent_phase_for<Heat>(P, q, grid, st);
+    if (scheme == 1) return persistent_phase_for<KS>(P, q, grid, st);
+    return persistent_phase_for<Euler>(P, q, grid, st);
+}
+
+int persistent_blocks_per_cu(int scheme, int P)
+{
+    if (scheme == 0) return persistent_blocks_for<Heat>(P);
+    if (scheme == 1) return persistent_blocks_for<KS>(P);
+    return persistent_blocks_for<Euler>(P);
+}
+
+hipError_t launch_zero_words(void *p, int64_t count, hipStream_t st)
+{
+    if (count <= 0) return hipSuccess;
+    const int64_t blocks = std::min<int64_t>((count + 255) / 256, 4096);
+    hipLaunchKernelGGL(zero_words, dim3((unsigned)blocks), dim3(256), 0, st, (uint32_t *)p, count);
+    return hipGetLastError();
 }
 
 hipError_t launch_advance_phases(SolveDesc *desc, int64_t n, hipStream_t st)

@@ -9,8 +9,8 @@
 // keep their previous contents, which is what lets a tile keep its edges in place.
 // With SEL every point is computed and the written ones are selected afterwards,
 // so the P independent updates form one block the compiler can interleave (hides
-// FP64 latency when few waves are resident); without it each point is a branch,
-// which costs fewer vector instructions when a point is cheap (heat).
+// FP64 latency when few waves are resident); without it each point is a branch
+// (exec-masked regions), which the host evaluation of single points uses.
 //
 //   Heat  (Appendix B, Eq. Heatdisc):  T' = Fo (T_{i+1} + T_{i-1}) + (1 - 2 Fo) T_i,
 //         the Fo product fused with the addition
@@ -55,7 +55,7 @@ SW_HD double sw_fabs(double x) { return fabs(x); }
 
 struct Heat {
     static constexpr int R = 1, S = 1, NV = 1;
-    static constexpr bool SELECT_ONE_WAVE = false;  // 4 operations per point: branch instead
+    static constexpr bool SELECT_ONE_WAVE = true;
     static constexpr bool LANE_EXCHANGE = false;    // no per-cell quantity shared by neighbours
     template <int P, bool SEL = true>
     SW_HD static void level(double (&dst)[NV][P], const double (&ext)[NV][P + 2 * R],

@@ -596,15 +596,105 @@ __global__ __launch_bounds__(64) void batch_tiles(const SolveDesc *__restrict__ 
     }
 }
 
+// Persistent batched launch (ensemble): one-wave work-groups take entries from one
+// counter in phase-major order -- every (solve, tile) of phase 0, then of phase 1,
+// ... -- and run each as soon as the tiles of the previous phase whose outputs it
+// reads (phase_deps) are done: no launch per phase and no grid-wide barrier, the
+// GPU-side synchronisation the paper's Conclusions suggest in place of kernel
+// launches.  Completion counters are published with agent-scope release and read
+// with agent-scope acquire, which writes back and invalidates the XCD-private L2
+// caches as needed.  Entry i of phase p is items[i - phase_start[p]]; its tile's
+// counter is done[i - phase_start[p]].  Phase-major order makes every dependency an
+// earlier entry, so the work-group holding the earliest unfinished entry can always
+// proceed; a wait that runs past spin_limit polls (never in a correct run) sets
+// *error and gives up instead of hanging.
 template <class Sch, int P>
-hipError_t launch_tile(const TileArgs &a, int threads, hipStream_t st)
+__global__ __launch_bounds__(64) void batch_persistent(PersistArgs q)
+{
+    __shared__ double stage[2 * Sch::NV * wave_span(P)];
+    __shared__ unsigned long long entry;
+    const int lane = (int)threadIdx.x;
+    const int64_t total = q.phase_start[q.max_phases];
+    for (;;) {
+        if (lane == 0) entry = atomicAdd(q.next, 1ull);
+        __syncthreads();
+        const int64_t i = (int64_t)entry;
+        __syncthreads();   // every lane has read `entry` before lane 0 takes the next one
+        if (i >= total) break;
+        int lo = 0, hi = q.max_phases;   // phase_start[lo] <= i < phase_start[hi]
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (q.phase_start[mid] <= i) lo = mid;
+            else hi = mid;
+        }
+        const int p = lo;
+        const int64_t r = i - q.phase_start[p];
+        const int2 it = q.items[r];
+        const SolveDesc &d = q.desc[it.x];
+        const int64_t base = r - it.y;   // counter of the solve's tile 0
+        if (p > 0) {
+            int64_t deps[2];
+            const int nd = phase_deps(d.Q, d.rem, d.H, d.K, p, it.y, deps);
+            for (int k = 0; k < nd; ++k) {
+                int64_t spins = 0;
+                while (__hip_atomic_load(q.done + base + deps[k], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < p) {
+                    if (++spins > q.spin_limit) {
+                        if (lane == 0) atomicOr(q.error, 1);
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(2);
+                }
+            }
+        }
+        TileArgs a;
+        a.state = d.state;
+        a.edges = d.edges;
+        a.n = d.n;
+        a.K = d.K;
+        a.w = d.w;
+        a.H = d.H;
+        a.E = d.E;
+        a.bc = d.bc;
+        a.ends = 0;
+        a.c = d.c;
+        phase_at(d.Q, d.rem, d.H, p, a.kind, a.levels, a.offset);
+        wave_tile<Sch, P>(a, (int64_t)it.y, lane, stage);
+        if (lane == 0) {
+            // the release orders every store of this one-wave work-group before the counter
+            __hip_atomic_store(q.done + r, p + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            if (p + 1 == d.nphases && atomicAdd(q.finished + it.x, 1) + 1 == d.K)
+                q.stamps[it.x] = wall_clock64();   // the solve's last tile is done
+        }
+    }
+}
+
+template <class Sch, int P>
+hipError_t persistent_launch_t(const PersistArgs &q, int grid, hipStream_t st)
+{
+    hipLaunchKernelGGL((batch_persistent<Sch, P>), dim3((unsigned)grid), dim3(64), 0, st, q);
+    return hipGetLastError();
+}
+
+template <class Sch, int P>
+int persistent_occupancy_t()
+{
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, batch_persistent<Sch, P>, 64, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        return 1;
+    }
+    return n > 0 ? n : 1;
+}
+
+template <class Sch, int P>
+hipError_t launch_tile(const TileArgs &a, int threads, hipStream_t st, int64_t tiles)
 {
     constexpr int MAXT = max_threads_for(Sch::NV, P);
     if (threads > MAXT) return hipErrorInvalidValue;
     if (threads == 64)
-        hipLaunchKernelGGL((swept_tile<Sch, P, 64>), dim3((unsigned)a.K), dim3(64), 0, st, a);
+        hipLaunchKernelGGL((swept_tile<Sch, P, 64>), dim3((unsigned)tiles), dim3(64), 0, st, a);
     else
-        hipLaunchKernelGGL((swept_tile<Sch, P, MAXT>), dim3((unsigned)a.K), dim3(threads), 0, st, a);
+        hipLaunchKernelGGL((swept_tile<Sch, P, MAXT>), dim3((unsigned)tiles), dim3(threads), 0, st, a);
     return hipGetLastError();
 }
 
@@ -631,14 +721,14 @@ int batch_occupancy_t()
 }  // namespace
 
 template <class Sch>
-hipError_t swept_phase_for(int P, int threads, const TileArgs &a, hipStream_t st)
+hipError_t swept_phase_for(int P, int threads, const TileArgs &a, hipStream_t st, int64_t tiles)
 {
     switch (P) {
-    case 1: return launch_tile<Sch, 1>(a, threads, st);
-    case 2: return launch_tile<Sch, 2>(a, threads, st);
-    case 4: return launch_tile<Sch, 4>(a, threads, st);
-    case 8: return launch_tile<Sch, 8>(a, threads, st);
-    case 16: if constexpr (Sch::NV == 1) return launch_tile<Sch, 16>(a, threads, st); break;
+    case 1: return launch_tile<Sch, 1>(a, threads, st, tiles);
+    case 2: return launch_tile<Sch, 2>(a, threads, st, tiles);
+    case 4: return launch_tile<Sch, 4>(a, threads, st, tiles);
+    case 8: return launch_tile<Sch, 8>(a, threads, st, tiles);
+    case 16: if constexpr (Sch::NV == 1) return launch_tile<Sch, 16>(a, threads, st, tiles); break;
     default: break;
     }
     return hipErrorInvalidValue;
@@ -654,6 +744,30 @@ hipError_t batch_phase_for(int P, const SolveDesc *desc, const int2 *items, int6
     case 4: return batch_launch_t<Sch, 4>(desc, items, nitems, global_phase, grid, st);
     case 8: return batch_launch_t<Sch, 8>(desc, items, nitems, global_phase, grid, st);
     default: return hipErrorInvalidValue;
+    }
+}
+
+template <class Sch>
+hipError_t persistent_phase_for(int P, const PersistArgs &q, int grid, hipStream_t st)
+{
+    switch (P) {
+    case 1: return persistent_launch_t<Sch, 1>(q, grid, st);
+    case 2: return persistent_launch_t<Sch, 2>(q, grid, st);
+    case 4: return persistent_launch_t<Sch, 4>(q, grid, st);
+    case 8: return persistent_launch_t<Sch, 8>(q, grid, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <class Sch>
+int persistent_blocks_for(int P)
+{
+    switch (P) {
+    case 1: return persistent_occupancy_t<Sch, 1>();
+    case 2: return persistent_occupancy_t<Sch, 2>();
+    case 4: return persistent_occupancy_t<Sch, 4>();
+    case 8: return persistent_occupancy_t<Sch, 8>();
+    default: return 1;
     }
 }
 

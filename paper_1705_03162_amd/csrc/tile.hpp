@@ -102,6 +102,29 @@ SW_HD void phase_at(int64_t Q, int64_t rem, int H, int64_t p, int32_t &kind, int
     offset = q == 0 ? 0 : 1;
 }
 
+// Tiles of phase p - 1 (p >= 1) whose outputs tile j of phase p reads, written to
+// deps[0..count).  A Diamond or Down tile at offset o reads slots 2j + o and
+// 2j + o + 1, written by the previous phase (offset 1 - o) as tiles j, j + 1
+// (o = 1) or j - 1, j (o = 0).  A remainder Up reads the state, whose points
+// [j w, j w + w) the previous Down wrote as tile j (offset 0) or tiles j - 1, j
+// (offset 1).  The same tiles were the last to read the slots and points that
+// tile j rewrites, so these are also its write-after-read dependencies.
+SW_HD int phase_deps(int64_t Q, int64_t rem, int H, int64_t K, int64_t p, int64_t j, int64_t deps[2])
+{
+    int32_t kind, levels, off, kind0, levels0, off0;
+    phase_at(Q, rem, H, p, kind, levels, off);
+    phase_at(Q, rem, H, p - 1, kind0, levels0, off0);
+    const int64_t left = j == 0 ? K - 1 : j - 1, right = j + 1 == K ? 0 : j + 1;
+    if (kind == PH_UP) {
+        if (off0 == 0) { deps[0] = j; return 1; }
+        deps[0] = left; deps[1] = j;
+        return 2;
+    }
+    if (off == 1) { deps[0] = j; deps[1] = right; }
+    else { deps[0] = left; deps[1] = j; }
+    return 2;
+}
+
 // Number of levels a tile computes in this launch.
 SW_HD int tile_levels(const TileArgs &a)
 {

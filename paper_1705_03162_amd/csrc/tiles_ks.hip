@@ -4,8 +4,10 @@
 
 namespace sw {
 
-template hipError_t swept_phase_for<KS>(int, int, const TileArgs &, hipStream_t);
+template hipError_t swept_phase_for<KS>(int, int, const TileArgs &, hipStream_t, int64_t);
 template hipError_t batch_phase_for<KS>(int, const SolveDesc *, const int2 *, int64_t, int, int, hipStream_t);
 template int batch_blocks_for<KS>(int);
+template hipError_t persistent_phase_for<KS>(int, const PersistArgs &, int, hipStream_t);
+template int persistent_blocks_for<KS>(int);
 
 }  // namespace sw

@@ -121,14 +121,54 @@ def test_default_shape_divides_n(lib):
         lib.swept_plan_destroy(h)
 
 
-def _table():
+def _table(kind="swept"):
+    """Rows of the tuning table: swept (scheme, log2n) -> (width, threads), or classic
+    (scheme, log2n) -> threads."""
     out = {}
     with open(os.path.join(ROOT, "paper_1705_03162_amd", "tune_gfx950.txt")) as f:
         for line in f:
-            if line.strip() and not line.startswith("#"):
-                s, lg, w, t = (int(x) for x in line.split()[:4])
+            parts = line.split()
+            if not parts or parts[0].startswith("#"):
+                continue
+            if parts[0] == "classic":
+                if kind == "classic":
+                    out[(int(parts[1]), int(parts[2]))] = int(parts[3])
+            elif kind == "swept":
+                s, lg, w, t = (int(x) for x in parts[:4])
                 out[(s, lg)] = (w, t)
     return out
+
+
+def test_classic_threads_from_the_table_or_the_tuning(lib):
+    """The classic work-group size comes from the table's classic row for the size
+    class, or from sw_tuning.classic_threads when given; illegal sizes are rejected."""
+    table = _table("classic")
+    assert table, "the tuning table holds classic rows"
+    for (scheme, lg), t in sorted(table.items())[:6]:
+        n = 1 << lg
+        prob = (W.heat_problem(n, 10) if scheme == W.HEAT else
+                W.ks_problem(n, 10) if scheme == W.KS else W.sod_problem(n, 10))
+        rc, h = _plan(lib, prob)
+        assert rc == 0
+        assert _info(lib, h).classic_threads == t, (scheme, lg)
+        lib.swept_plan_destroy(h)
+    p = N.problem_struct(W.heat_problem(4096, 10))
+    for ct, ok in ((128, True), (1024, True), (96, False), (2048, False)):
+        tun = N.SwTuning(0, 0, 0, ct)
+        h = ctypes.c_void_p()
+        rc = lib.swept_plan(ctypes.byref(p), ctypes.byref(tun), ctypes.byref(h))
+        assert (rc == 0) == ok, ct
+        if ok:
+            assert _info(lib, h).classic_threads == ct
+            lib.swept_plan_destroy(h)
+
+
+def test_hybrid_flag_accepted_and_unknown_flags_rejected(lib):
+    rc, h = _plan(lib, W.sod_problem(4096, 10), flags=N.SW_TUNE_HYBRID)
+    assert rc == 0
+    lib.swept_plan_destroy(h)
+    rc, _ = _plan(lib, W.sod_problem(4096, 10), flags=64)
+    assert rc == N.SW_EINVAL
 
 
 def test_tuned_shapes_from_nearest_measured_class(lib):

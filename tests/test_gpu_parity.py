@@ -384,3 +384,42 @@ def test_large_dirichlet_heat_and_sod_swept_equals_classic():
                      (W.heat_problem(1 << 18, 5000, bc=W.REFLECTIVE), W.fourier_ic(1 << 18, 4)),
                      (W.sod_problem(1 << 16, 3000), W.sod_ic(1 << 16))):
         assert np.array_equal(gpu_solve(prob, ic, "swept"), gpu_solve(prob, ic, "classic"))
+
+
+# ------------------------------------------------------------------ Hybrid variant
+
+HYBRID = [  # non-periodic problems: the host computes the straddling tile of every shifted phase
+    (lambda: (W.heat_problem(4096, 2000, bc=W.REFLECTIVE), W.fourier_ic(4096, 41)), 512, 64),
+    (lambda: (W.heat_problem(1 << 16, 3000, bc=W.REFLECTIVE), W.fourier_ic(1 << 16, 42)), 0, 0),
+    (lambda: (W.heat_problem(2048, 999, bc=W.DIRICHLET, bc_left=0.3, bc_right=-0.6), W.fourier_ic(2048, 43)),
+     256, 128),
+    (lambda: (W.heat_problem(1024, 333, bc=W.REFLECTIVE), W.fourier_ic(1024, 44)), 1024, 64),   # K = 1
+    (lambda: (W.Problem(W.KS, 4096, 700, 2.0 ** -8, 0.5, bc=W.DIRICHLET, bc_left=(0.4, 0, 0),
+                        bc_right=(-0.2, 0, 0)), W.fourier_ic(4096, 45)), 1024, 64),
+    (lambda: (W.sod_problem(4096, 1200), W.sod_ic(4096)), 256, 64),
+    (lambda: (W.sod_problem(1 << 14), W.sod_ic(1 << 14)), 0, 0),                           # to t = 0.2
+]
+
+
+@pytest.mark.parametrize("case", range(len(HYBRID)))
+def test_hybrid_equals_swept_and_oracle(oracle_mod, case):
+    """Hybrid variant (Sec. 5.1): the straddling tile on the host, the rest on the GPU;
+    bit-identical to the all-GPU swept solve and to the oracle."""
+    factory, width, threads = HYBRID[case]
+    prob, ic = factory()
+    got = gpu_solve(prob, ic, "swept", width, threads, flags=sw.SW_TUNE_HYBRID)
+    assert np.array_equal(got, gpu_solve(prob, ic, "swept", width, threads))
+    assert np.array_equal(got.reshape(prob.nvars, prob.n), oracle_mod.solve(prob, ic))
+
+
+def test_hybrid_repeated_solves_on_one_plan():
+    """Two hybrid solves in a row on one plan (the second waits for the first's host work)."""
+    prob, ic = W.heat_problem(8192, 1500, bc=W.REFLECTIVE), W.fourier_ic(8192, 46)
+    with sw.Plan(prob, 512, 64, sw.SW_TUNE_HYBRID) as plan:
+        a = torch.tensor(ic, dtype=torch.float64, device=DEV)
+        b = a.clone()
+        plan.swept(a)
+        plan.swept(b)
+        torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    assert np.array_equal(a.cpu().numpy(), gpu_solve(prob, ic, "swept", 512, 64))

@@ -20,13 +20,15 @@ from paper_1705_03162_amd._native import SwProblem, problem_struct
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SRC = os.path.join(HERE, "hostsim", "hostsim.cpp")
+# the library's host routine of the Hybrid variant, tested here on the CPU
+HYBRID_SRC = os.path.join(ROOT, "paper_1705_03162_amd", "csrc", "hybrid.cpp")
 LIB = os.path.join(HERE, "hostsim", "libhostsim.so")
 
 
 def build_hostsim():
     cmd = ["g++", "-O2", "-std=c++17", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
            "-Wno-unknown-pragmas", "-I", os.path.join(ROOT, "include"),
-           "-I", os.path.join(ROOT, "paper_1705_03162_amd", "csrc"), SRC, "-o", LIB + ".tmp"]
+           "-I", os.path.join(ROOT, "paper_1705_03162_amd", "csrc"), SRC, HYBRID_SRC, "-o", LIB + ".tmp"]
     subprocess.run(cmd, check=True)
     os.replace(LIB + ".tmp", LIB)
 
@@ -38,6 +40,12 @@ def hostsim():
     L.hostsim_swept.argtypes = [ctypes.POINTER(SwProblem), ctypes.c_int, ctypes.c_int,
                                 ctypes.POINTER(ctypes.c_double)]
     L.hostsim_swept.restype = ctypes.c_int
+    L.hostsim_swept_mode.argtypes = [ctypes.POINTER(SwProblem), ctypes.c_int, ctypes.c_int,
+                                     ctypes.POINTER(ctypes.c_double), ctypes.c_int]
+    L.hostsim_swept_mode.restype = ctypes.c_int
+    L.hostsim_dataflow.argtypes = [ctypes.POINTER(SwProblem), ctypes.c_int, ctypes.c_int,
+                                   ctypes.POINTER(ctypes.c_double), ctypes.c_uint64]
+    L.hostsim_dataflow.restype = ctypes.c_int
     L.hostsim_phases.argtypes = [ctypes.POINTER(SwProblem), ctypes.c_int, ctypes.c_int,
                                  ctypes.POINTER(ctypes.c_int32), ctypes.c_int]
     L.hostsim_phases.restype = ctypes.c_int
@@ -150,3 +158,58 @@ def test_phase_sequence_shape(hostsim):
     ph = phases(hostsim, W.ks_problem(1 << 20, 50_000), 1024, 64)
     # 100,000 levels = 390 phases of 256 + 160: Up, 389 Diamonds, Down, Up(160), Down(160)
     assert ph[0] == (0, 256, 0) and len(ph) == 393 and ph[-2:] == [(0, 160, 0), (2, 160, 1)]
+
+
+HYBRID_CASES = [  # (problem, ic, width, threads): non-periodic, with full phases and remainders
+    (W.heat_problem(1024, 777, bc=W.REFLECTIVE), W.fourier_ic(1024, 31), 128, 64),
+    (W.heat_problem(2048, 1301, bc=W.DIRICHLET, bc_left=0.25, bc_right=-0.5), W.fourier_ic(2048, 32), 256, 64),
+    (W.heat_problem(512, 200, bc=W.REFLECTIVE), W.fourier_ic(512, 33), 512, 64),       # K = 1
+    (W.Problem(W.KS, 1024, 333, 2.0 ** -8, 0.5, bc=W.DIRICHLET, bc_left=(0.4, 0, 0), bc_right=(-0.2, 0, 0)),
+     W.fourier_ic(1024, 34), 256, 64),
+    (W.sod_problem(1024, 450), W.sod_ic(1024), 128, 64),
+    (W.sod_problem(2048, 97), W.sod_ic(2048), 512, 64),
+]
+
+
+@pytest.mark.parametrize("case", range(len(HYBRID_CASES)))
+def test_hybrid_host_tile_equals_oracle(hostsim, oracle_mod, case):
+    """Hybrid variant: with the straddling tile of every shifted phase computed by the
+    library's host routine (hybrid_tile_host) and the other tiles by the emulated
+    work-group, the result still equals the oracle bit for bit."""
+    prob, ic, width, threads = HYBRID_CASES[case]
+    out = np.array(ic, dtype=np.float64, copy=True, order="C")
+    s = problem_struct(prob)
+    rc = hostsim.hostsim_swept_mode(ctypes.byref(s), width, threads,
+                                    out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), 1)
+    assert rc == 0, rc
+    assert np.array_equal(out.reshape(prob.nvars, prob.n), oracle_mod.solve(prob, ic))
+
+
+DATAFLOW_CASES = [  # several tiles, full phases and remainders, every boundary type, Q = 0 and 1
+    (W.heat_problem(1024, 333), W.fourier_ic(1024, 51), 128, 64),
+    (W.heat_problem(1024, 40), W.fourier_ic(1024, 52), 128, 64),            # fewer levels than a phase
+    (W.heat_problem(512, 100, bc=W.REFLECTIVE), W.fourier_ic(512, 53), 64, 64),
+    (W.ks_problem(1024, 301), W.fourier_ic(1024, 54), 128, 64),
+    (W.ks_problem(512, 16), W.fourier_ic(512, 55), 64, 64),                  # Q = 1 and a remainder
+    (W.Problem(W.KS, 512, 200, 2.0 ** -8, 0.5, bc=W.DIRICHLET, bc_left=(0.4, 0, 0), bc_right=(-0.2, 0, 0)),
+     W.fourier_ic(512, 56), 128, 64),
+    (W.sod_problem(512, 150), W.sod_ic(512), 64, 64),
+    (W.heat_problem(256, 77), W.fourier_ic(256, 57), 256, 64),               # K = 1
+]
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+@pytest.mark.parametrize("case", range(len(DATAFLOW_CASES)))
+def test_dataflow_order_equals_oracle(hostsim, oracle_mod, case, seed):
+    """The persistent batched kernel runs a tile as soon as the tiles of the previous
+    phase named by phase_deps are done.  Tiles executed in random orders that respect
+    only those dependencies (not the phase order) give the oracle's result bit for bit,
+    so the dependencies cover every read-after-write and write-after-read between
+    phases (edge slots and state)."""
+    prob, ic, width, threads = DATAFLOW_CASES[case]
+    out = np.array(ic, dtype=np.float64, copy=True, order="C")
+    s = problem_struct(prob)
+    rc = hostsim.hostsim_dataflow(ctypes.byref(s), width, threads,
+                                  out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), seed)
+    assert rc == 0, rc
+    assert np.array_equal(out.reshape(prob.nvars, prob.n), oracle_mod.solve(prob, ic))
