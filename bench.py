@@ -146,17 +146,13 @@ def pct(xs, q):
     return float(np.percentile(np.asarray(xs), q)) if len(xs) else None
 
 
-def ensemble_run(count=4096, nsteps=10_000, one_at_a_time_sample=512):
-    """4096 independent heat/KS solves of uneven N: one batched graph launch vs
-    the same solves one after another (each its own tuned plan), on the same GPU."""
-    import torch
-    import paper_1705_03162_amd as sw
-    members = W.ensemble(count=count, nsteps=nsteps)
-    ics = [W.ensemble_ic(m) for m in members]
+def batched_ensemble(sw, torch, members, ics, persistent):
+    """One batch_run over every member (one graph launch), timed by the host clock;
+    completion latency per solve from the library's device stamps."""
     upd = sum(m.problem.point_updates for m in members)
     states = [torch.tensor(ic, dtype=torch.float64, device="cuda") for ic in ics]
     torch.cuda.synchronize()
-    with sw.Batch(budget_bytes=200 << 30) as b:
+    with sw.Batch(budget_bytes=200 << 30, persistent=persistent) as b:
         tickets = [b.submit(m.problem, x) for m, x in zip(members, states)]
         t0 = time.perf_counter()
         b.run()
@@ -165,8 +161,23 @@ def ensemble_run(count=4096, nsteps=10_000, one_at_a_time_sample=512):
         infos = [b.info(t) for t in tickets]
     start = min(i["start_s"] for i in infos)
     lat = [i["end_s"] - start for i in infos]
-    batched = {"solves": count, "point_updates": upd, "seconds": makespan, "rate": upd / makespan,
-               "p50_s": pct(lat, 50), "p99_s": pct(lat, 99)}
+    return {"solves": len(members), "point_updates": upd, "seconds": makespan, "rate": upd / makespan,
+            "p50_s": pct(lat, 50), "p99_s": pct(lat, 99)}, states
+
+
+def ensemble_run(count=4096, nsteps=10_000, one_at_a_time_sample=512):
+    """4096 independent heat/KS solves of uneven N: one batched graph launch (one launch
+    per phase index, and the persistent variant with device-side dependency counters)
+    vs the same solves one after another (each its own tuned plan), on the same GPU."""
+    import torch
+    import paper_1705_03162_amd as sw
+    members = W.ensemble(count=count, nsteps=nsteps)
+    ics = [W.ensemble_ic(m) for m in members]
+    upd = sum(m.problem.point_updates for m in members)
+    batched, out_l = batched_ensemble(sw, torch, members, ics, persistent=False)
+    persist, out_p = batched_ensemble(sw, torch, members, ics, persistent=True)
+    same = all(torch.equal(a, b) for a, b in zip(out_l, out_p))
+    del out_l, out_p
     # one solve at a time: a seeded sample, extrapolated by point-updates
     rng = np.random.default_rng(7)
     idx = rng.choice(count, size=min(one_at_a_time_sample, count), replace=False)
@@ -188,59 +199,13 @@ def ensemble_run(count=4096, nsteps=10_000, one_at_a_time_sample=512):
     alone_rate = upd_alone / t_alone
     # FIFO completion times if every solve ran alone, back to back from t = 0
     est = upd / alone_rate
-    return {"batched": batched,
+    best = max(batched["rate"], persist["rate"])
+    return {"batched": batched, "batched_persistent": persist, "persistent_equals_lockstep": bool(same),
+            "faster": "persistent" if persist["rate"] > batched["rate"] else "lockstep",
             "one_at_a_time": {"sampled_solves": len(idx), "rate": alone_rate,
                               "estimated_seconds": est, "solve_p50_s": pct(lat_alone, 50),
                               "solve_p99_s": pct(lat_alone, 99)},
-            "speedup": batched["rate"] / alone_rate}
-
-
-def serve_run(rate=2000.0, duration_s=0.25, seed=5, max_slots=0, fifo=True):
-    """Poisson arrivals of mixed heat/KS/Sod solves into a served batch (continuous
-    batching, 200 GB budget); latency = completion - arrival."""
-    import torch
-    import paper_1705_03162_amd as sw
-    trace = W.poisson_trace(rate=rate, duration_s=duration_s, seed=seed)
-    ics = [W.request_ic(r) for r in trace]
-    states = [torch.tensor(ic, dtype=torch.float64, device="cuda") for ic in ics]
-    torch.cuda.synchronize()
-    upd = sum(r.problem.point_updates for r in trace)
-    with sw.Batch(budget_bytes=200 << 30, max_slots=max_slots, serve=True) as b:
-        t0 = time.perf_counter()
-        tickets = []
-        for r, x in zip(trace, states):
-            delay = r.arrival_s - (time.perf_counter() - t0)
-            if delay > 0:
-                time.sleep(delay)
-            tickets.append(b.submit(r.problem, x))
-        for t in tickets:
-            b.wait(t)
-        wall = time.perf_counter() - t0
-        infos = [b.info(t) for t in tickets]
-    lat = [i["end_s"] - i["submit_s"] for i in infos]
-    out = {"requests": len(trace), "offered_rate_per_s": rate, "arrival_window_s": duration_s,
-           "point_updates": upd, "wall_s": wall, "throughput_point_updates_s": upd / wall,
-           "p50_latency_s": pct(lat, 50), "p99_latency_s": pct(lat, 99)}
-    if fifo:
-        # one solve at a time, first come first served, on the same trace
-        lat_f = []
-        t0 = time.perf_counter()
-        for r, ic in zip(trace, ics):
-            now = time.perf_counter() - t0
-            if now < r.arrival_s:
-                time.sleep(r.arrival_s - now)
-            with sw.Plan(r.problem, flags=sw.SW_TUNE_NO_GRAPH) as plan:
-                x = torch.tensor(ic, dtype=torch.float64, device="cuda")
-                if plan.info()["swept_ok"]:
-                    plan.swept(x)
-                else:
-                    plan.classic(x)
-                torch.cuda.synchronize()
-            lat_f.append(time.perf_counter() - t0 - r.arrival_s)
-        wall_f = time.perf_counter() - t0
-        out["one_at_a_time"] = {"wall_s": wall_f, "throughput_point_updates_s": upd / wall_f,
-                                "p50_latency_s": pct(lat_f, 50), "p99_latency_s": pct(lat_f, 99)}
-    return out
+            "speedup": best / alone_rate}
 
 
 def legal_p(scheme):
@@ -496,41 +461,45 @@ def served(torch, sw, trace, warmup_s=0.0, max_slots=0):
             "arrival_window_s": window}
 
 
-def suite_serve(rate=2000.0, duration_s=10.0, warmup_s=1.0, fifo_prefix=300):
+def serve_configured(rate=2000.0, duration_s=10.0, warmup_s=1.0, fifo_prefix=300,
+                     rates=(100.0, 150.0, 200.0, 250.0, 300.0, 400.0), window=5.0, emit=None):
     """The configured serving run (Poisson arrivals at `rate` for `duration_s` after
-    `warmup_s`, then drain), the highest rate with a stable queue, and one solve at
-    a time, first come first served, on a prefix of the configured trace."""
+    `warmup_s`, then drain), the highest rate with a stable queue, and one solve at a
+    time, first come first served, on a prefix of the configured trace.  Returns one
+    dict; `emit`, if given, receives each partial result as it is measured."""
     import torch
     import paper_1705_03162_amd as sw
+    emit = emit or (lambda d: None)
     trace = W.poisson_trace(rate=rate, duration_s=warmup_s + duration_s, seed=5)
     log(f"serve: configured {rate}/s, {len(trace)} requests ...")
-    res = served(torch, sw, trace, warmup_s=warmup_s)
-    res.update({"run": "configured", "offered_rate_per_s": rate})
-    print(json.dumps(res), flush=True)
+    conf = served(torch, sw, trace, warmup_s=warmup_s)
+    conf.update({"run": "configured", "offered_rate_per_s": rate, "warmup_s": warmup_s})
+    emit(conf)
 
-    # sustainable rate: ascending offered rates on 5 s traces.  With a budget this
+    # sustainable rate: ascending offered rates on short traces.  With a budget this
     # large every request is resident at once, so an overloaded server shows up as
     # a long drain after the last arrival, not as a queue: a rate is sustainable
-    # when the drain takes at most max(2 s, half the window).  (Latency by arrival
-    # time is reported too; with a few hundred heavy-tailed requests it is too
-    # noisy to decide on.)
-    stable = None
-    window = 5.0
-    for r in (25.0, 50.0, 75.0, 100.0, 150.0, 200.0, 300.0):
+    # when the drain takes at most max(2 s, half the window).
+    stable, searched = None, []
+    for r in rates:
         tr = W.poisson_trace(rate=r, duration_s=window, seed=6)
         x = served(torch, sw, tr)
         drain = x["wall_s"] - max(q.arrival_s for q in tr)
         x["drain_s"] = drain
         ok = drain <= max(2.0, 0.5 * window)
         x.update({"run": "rate_search", "offered_rate_per_s": r, "stable": ok})
-        print(json.dumps(x), flush=True)
+        searched.append({"rate_per_s": r, "stable": ok, "drain_s": drain, "p50_latency_s": x["p50_latency_s"],
+                         "p99_latency_s": x["p99_latency_s"]})
+        emit(x)
         log(f"serve rate {r}/s: stable={ok} p50 {x['p50_latency_s']:.3f} s p99 {x['p99_latency_s']:.3f} s")
         if not ok:
             break
         stable = x
-    print(json.dumps({"run": "sustainable", "rate_per_s": None if stable is None else stable["offered_rate_per_s"],
-                      "p50_latency_s": None if stable is None else stable["p50_latency_s"],
-                      "p99_latency_s": None if stable is None else stable["p99_latency_s"]}), flush=True)
+    sustainable = {"rate_per_s": None if stable is None else stable["offered_rate_per_s"],
+                   "p50_latency_s": None if stable is None else stable["p50_latency_s"],
+                   "p99_latency_s": None if stable is None else stable["p99_latency_s"],
+                   "throughput_point_updates_s": None if stable is None else stable["throughput_point_updates_s"],
+                   "window_s": window, "searched": searched}
 
     # one solve at a time, FIFO, on the configured trace's first requests
     pre = trace[:fifo_prefix]
@@ -550,9 +519,24 @@ def suite_serve(rate=2000.0, duration_s=10.0, warmup_s=1.0, fifo_prefix=300):
             torch.cuda.synchronize()
         lat.append(time.perf_counter() - t0 - r.arrival_s)
     wall = time.perf_counter() - t0
-    print(json.dumps({"run": "fifo_one_at_a_time", "requests": len(pre), "offered_rate_per_s": rate,
-                      "wall_s": wall, "throughput_point_updates_s": upd / wall,
-                      "p50_latency_s": pct(lat, 50), "p99_latency_s": pct(lat, 99)}), flush=True)
+    fifo = {"run": "fifo_one_at_a_time", "requests": len(pre), "offered_rate_per_s": rate,
+            "wall_s": wall, "throughput_point_updates_s": upd / wall,
+            "p50_latency_s": pct(lat, 50), "p99_latency_s": pct(lat, 99)}
+    emit(fifo)
+    # the same prefix through the served batch, for a like-for-like comparison
+    pre_served = served(torch, sw, pre)
+    return {"configured": conf, "sustainable": sustainable, "fifo_prefix_one_at_a_time": fifo,
+            "fifo_prefix_served": {"requests": pre_served["requests"], "wall_s": pre_served["wall_s"],
+                                   "throughput_point_updates_s": pre_served["throughput_point_updates_s"],
+                                   "p50_latency_s": pre_served["p50_latency_s"],
+                                   "p99_latency_s": pre_served["p99_latency_s"]}}
+
+
+def suite_serve(rate=2000.0, duration_s=10.0, warmup_s=1.0, fifo_prefix=300):
+    """One JSON line per serving measurement (see serve_configured), then a summary."""
+    res = serve_configured(rate, duration_s, warmup_s, fifo_prefix, emit=lambda d: print(json.dumps(d), flush=True))
+    print(json.dumps({"run": "summary", "sustainable": res["sustainable"],
+                      "fifo_prefix_served": res["fifo_prefix_served"]}), flush=True)
 
 
 def suite_oracle(budget_s=6.0):
@@ -587,6 +571,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-batch", action="store_true", help="skip the ensemble and serving runs")
     ap.add_argument("--profile-reps", type=int, default=30)
+    ap.add_argument("--serve-window", type=float, default=10.0,
+                    help="arrival window (s, after a 1 s warm-up) of the configured serving run")
     ap.add_argument("--suite", default="main",
                     choices=["main", "sweep", "euler", "euler-full", "ensemble", "serve", "kernel",
                              "classic-kernel", "anchors", "oracle", "hybrid"],
@@ -786,12 +772,14 @@ def main():
     if not args.no_batch:
         log("ensemble (4096 solves) ...")
         result["batch"] = {"ensemble": ensemble_run()}
-        log("served Poisson trace ...")
-        result["batch"]["serve"] = serve_run(rate=2000.0, duration_s=0.25)
+        log("served Poisson traces (configured 2000/s for 10 s after 1 s, sustainable rate, FIFO) ...")
+        result["batch"]["serve"] = serve_configured(duration_s=args.serve_window)
         e = result["batch"]["ensemble"]
-        log(f"ensemble: batched {e['batched']['rate']:.3e} pt-upd/s in {e['batched']['seconds']:.2f} s, "
+        log(f"ensemble: batched {e['batched']['rate']:.3e} pt-upd/s in {e['batched']['seconds']:.2f} s "
+            f"(persistent {e['batched_persistent']['rate']:.3e} in {e['batched_persistent']['seconds']:.2f} s), "
             f"one-at-a-time {e['one_at_a_time']['rate']:.3e}; serve p50 "
-            f"{result['batch']['serve']['p50_latency_s']:.3f} s p99 {result['batch']['serve']['p99_latency_s']:.3f} s")
+            f"{result['batch']['serve']['configured']['p50_latency_s']:.3f} s p99 "
+            f"{result['batch']['serve']['configured']['p99_latency_s']:.3f} s")
     if not args.no_cpu:
         log("cpu baseline (oracle) ...")
         result["cpu_baseline"] = cpu_baseline()

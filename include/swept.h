@@ -190,12 +190,20 @@ int swept_solve_noalloc(const sw_problem *problem, const sw_tuning *tuning, doub
  * batching many solves of uneven n into shared phase launches, and serving
  * them continuously, are this library's additions around its swept phases.
  * Each solve keeps the exact results of swept_solve on the same problem. */
-#define SW_BATCH_SERVE 1          /* a worker thread admits and advances solves continuously */
+#define SW_BATCH_SERVE      1     /* a worker thread admits and advances solves continuously */
+#define SW_BATCH_PERSISTENT 2     /* ensemble: one persistent launch per tile group in which work-groups
+                                     take tiles from a device queue and wait on device-side completion
+                                     counters of the tiles they depend on, instead of one launch per
+                                     phase index (Sec. 7 suggests GPU-side synchronisation) */
 typedef struct {
-    int64_t budget_bytes;     /* device bytes the batch may hold for resident solves (state + edges,
-                                 counted as 3 * n * nvars * 8 per solve) */
+    int64_t budget_bytes;     /* device bytes the batch may hold for resident solves: each is charged
+                                 its state plus its edge slots rounded up to 256 bytes (swept), or
+                                 twice its state (classic fallback); batch_ticket_info reports it */
     int32_t max_slots;        /* maximum resident solves (0 = unlimited) */
-    int32_t flags;            /* 0 (ensemble: batch_run) or SW_BATCH_SERVE */
+    int32_t flags;            /* SW_BATCH_SERVE or SW_BATCH_PERSISTENT (ensemble), or 0 */
+    int32_t points_per_lane;  /* batched tiles are one wave wide; points per lane (1, 2, 4 or 8, at
+                                 most what divides n / 64) or 0 for the tuned choice per size class */
+    int32_t reserved;         /* must be 0 */
 } sw_batch_config;
 
 typedef struct {
@@ -204,6 +212,7 @@ typedef struct {
     int32_t width;            /* tile width used (swept) */
     int32_t phases;           /* swept phases of the solve */
     double  submit_s, start_s, end_s;  /* host steady-clock seconds: submitted, admitted, finished */
+    int64_t resident_bytes;   /* device bytes charged against the batch budget while resident */
 } sw_ticket_info;
 
 typedef struct sw_batch sw_batch;
@@ -219,9 +228,17 @@ typedef struct sw_batch sw_batch;
  * starts at once. */
 int  batch_create(const sw_batch_config *config, sw_batch **out);
 /* Queue one solve on caller-owned device state (layout as above; the caller keeps
- * it alive and untouched until the ticket is done).  SW_EBUSY if the solve alone
- * exceeds the budget.  Thread-safe. */
+ * it alive and untouched until the ticket is done).  The initial state must already
+ * be complete on the device when batch_submit is called (the batch runs on streams
+ * of its own: synchronise the stream that wrote the state first, or use
+ * batch_submit_async).  SW_EBUSY if the solve alone exceeds the budget.
+ * Thread-safe. */
 int  batch_submit(sw_batch *batch, const sw_problem *problem, double *d_state, uint64_t *ticket);
+/* As batch_submit, but the state may still be being written by work queued on
+ * hip_stream: the library records an event on that stream now, and the solve's
+ * first launch waits for it. */
+int  batch_submit_async(sw_batch *batch, const sw_problem *problem, double *d_state, void *hip_stream,
+                        uint64_t *ticket);
 /* Ensemble mode: run every queued solve to completion, then return
  * (synchronous).  Solves are admitted in submission order in waves that fit the
  * budget and slot limit; each wave runs as one HIP graph launch holding one

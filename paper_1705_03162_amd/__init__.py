@@ -125,23 +125,34 @@ def classic_solve(plan: Plan, state, stream=None):
 class Batch:
     """Independent solves admitted under a device-memory budget (batch_* API).
 
-    serve=False: queue solves with submit(), then run() executes them all (ensemble).
+    serve=False: queue solves with submit(), then run() executes them all (ensemble);
+    persistent=True runs each tile group as one persistent launch with device-side
+    dependency counters instead of one launch per phase index.
     serve=True: a worker thread admits and advances solves as they are submitted
     (continuous batching); use poll()/wait()/info().
+    points_per_lane: one-wave tile shape of every solve (0: tuned per size class).
     """
 
-    def __init__(self, budget_bytes: int, max_slots: int = 0, serve: bool = False):
-        cfg = N.SwBatchConfig(int(budget_bytes), int(max_slots), N.SW_BATCH_SERVE if serve else 0)
+    def __init__(self, budget_bytes: int, max_slots: int = 0, serve: bool = False,
+                 persistent: bool = False, points_per_lane: int = 0):
+        flags = (N.SW_BATCH_SERVE if serve else 0) | (N.SW_BATCH_PERSISTENT if persistent else 0)
+        cfg = N.SwBatchConfig(int(budget_bytes), int(max_slots), flags, int(points_per_lane), 0)
         h = ctypes.c_void_p()
         N.check(N.lib().batch_create(ctypes.byref(cfg), ctypes.byref(h)), "batch_create")
         self._h = h
         self._keep = {}
 
-    def submit(self, problem, state, limiter: int = 0) -> int:
+    def submit(self, problem, state, limiter: int = 0, stream=None, asynchronous: bool = False) -> int:
+        """Queue a solve.  asynchronous=True: the state may still be being written on
+        `stream` (default: torch's current stream); the solve waits for that work."""
         p = problem_struct(problem, limiter)
         t = ctypes.c_uint64()
-        N.check(N.lib().batch_submit(self._h, ctypes.byref(p), _state_ptr(state, problem),
-                                     ctypes.byref(t)), "batch_submit")
+        if asynchronous:
+            N.check(N.lib().batch_submit_async(self._h, ctypes.byref(p), _state_ptr(state, problem),
+                                               _stream_handle(stream), ctypes.byref(t)), "batch_submit_async")
+        else:
+            N.check(N.lib().batch_submit(self._h, ctypes.byref(p), _state_ptr(state, problem),
+                                         ctypes.byref(t)), "batch_submit")
         self._keep[t.value] = state
         return t.value
 

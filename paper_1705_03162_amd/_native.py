@@ -54,16 +54,18 @@ class SwPlanInfo(ctypes.Structure):
 
 class SwBatchConfig(ctypes.Structure):
     _fields_ = [("budget_bytes", ctypes.c_int64), ("max_slots", ctypes.c_int32),
-                ("flags", ctypes.c_int32)]
+                ("flags", ctypes.c_int32), ("points_per_lane", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
-SW_BATCH_SERVE = 1
+SW_BATCH_SERVE, SW_BATCH_PERSISTENT = 1, 2
 
 
 class SwTicketInfo(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("swept", ctypes.c_int32), ("width", ctypes.c_int32),
                 ("phases", ctypes.c_int32), ("submit_s", ctypes.c_double),
-                ("start_s", ctypes.c_double), ("end_s", ctypes.c_double)]
+                ("start_s", ctypes.c_double), ("end_s", ctypes.c_double),
+                ("resident_bytes", ctypes.c_int64)]
 
 
 def problem_struct(problem, limiter: int = 0) -> SwProblem:
@@ -102,6 +104,8 @@ SIGNATURES = {
     "batch_create": (ctypes.c_int, [ctypes.POINTER(SwBatchConfig), ctypes.POINTER(_VP)]),
     "batch_submit": (ctypes.c_int, [_VP, ctypes.POINTER(SwProblem), _VP,
                                     ctypes.POINTER(ctypes.c_uint64)]),
+    "batch_submit_async": (ctypes.c_int, [_VP, ctypes.POINTER(SwProblem), _VP, _VP,
+                                          ctypes.POINTER(ctypes.c_uint64)]),
     "batch_run": (ctypes.c_int, [_VP, _VP]),
     "batch_poll": (ctypes.c_int, [_VP, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int32)]),
     "batch_wait": (ctypes.c_int, [_VP, ctypes.c_uint64, ctypes.c_int64]),

@@ -34,6 +34,7 @@
 #include "kernels.hpp"
 #include "plan_core.hpp"
 #include "swept.h"
+#include "tune.hpp"
 
 using namespace sw;
 
@@ -67,18 +68,47 @@ struct Ticket {
     int32_t phase = 0;
     int32_t nphases = 0;
     int64_t admit_tick = -1;   // served: first tick of its group that includes it
+    hipEvent_t ready = nullptr;   // batch_submit_async: the state is complete on the device
+    sw_plan *plan = nullptr;      // served classic fallback in flight
+    hipEvent_t finished = nullptr;
 };
 
-int64_t resident_bytes(const sw_problem &p)
+// Make `st` wait until the ticket's initial state is complete (batch_submit_async).
+hipError_t wait_ready(const Ticket &t, hipStream_t st)
 {
-    return 3 * p.n * (int64_t)scheme_nvars(p.scheme) * (int64_t)sizeof(double);
+    return t.ready ? hipStreamWaitEvent(st, t.ready, 0) : hipSuccess;
+}
+
+void release_events(Ticket *t)
+{
+    if (t->ready) (void)hipEventDestroy(t->ready);
+    if (t->finished) (void)hipEventDestroy(t->finished);
+    t->ready = t->finished = nullptr;
+}
+
+constexpr size_t kArenaAlign = 256;
+
+// Device bytes a resident solve holds in the batch: its state plus, batched, its edge
+// slots as the arena hands them out (rounded to the arena's alignment), or, solved
+// classically, the plan's scratch (a second state array).
+int64_t resident_bytes(const sw_problem &p, bool swept, const Geom &g)
+{
+    const int64_t state = p.n * (int64_t)scheme_nvars(p.scheme) * (int64_t)sizeof(double);
+    if (!swept) return 2 * state;
+    const int64_t edges = g.edge_doubles * (int64_t)sizeof(double);
+    return state + (edges + (int64_t)kArenaAlign - 1) / (int64_t)kArenaAlign * (int64_t)kArenaAlign;
 }
 
 // Tile shape for a batched solve: one-wave tiles (no barriers), the most points
-// per lane (up to 8) that still divide n.
-bool batch_shape(const sw_problem &p, int *P, Geom *g)
+// per lane that divide n up to a cap -- the caller's points_per_lane, else the
+// tuned value for the size class, else 8.
+bool batch_shape(const sw_problem &p, int forced, int *P, Geom *g)
 {
+    int cap = 8;
+    if (forced > 0) cap = forced;
+    else if (int t = 0; tuned_batch_points(p, &t) && t > 0) cap = t;
     for (int pp = 8; pp >= 1; pp /= 2) {
+        if (pp > cap) continue;
         if (!legal_points_per_lane(p.scheme, pp)) continue;
         const int w = 64 * pp;
         if (p.n % w != 0) continue;
@@ -95,7 +125,7 @@ struct Arena {
     struct Chunk { char *base; size_t size; std::map<size_t, size_t> free; };  // offset -> size
     std::vector<Chunk> chunks;
     static constexpr size_t kChunk = (size_t)256 << 20;
-    static constexpr size_t kAlign = 256;
+    static constexpr size_t kAlign = kArenaAlign;
 
     void *alloc(size_t bytes)
     {
@@ -148,6 +178,7 @@ struct Arena {
 // Device copy of one group's descriptors and (solve, tile) items.
 struct GroupBuf {
     int scheme = 0, P = 1;
+    std::vector<Ticket *> members;  // solves in table order
     std::vector<SolveDesc> desc;
     std::vector<int2> items;
     std::vector<int64_t> prefix;   // items of the first k solves
@@ -220,20 +251,146 @@ Ticket *find_ticket(sw_batch *b, uint64_t id)
     return &b->tickets[id - 1];
 }
 
-// Run a set of admitted swept tickets to completion as one graph (ensemble mode).
+// Device resources of one ensemble wave; release() frees whatever was allocated.
+struct EnsembleRun {
+    std::vector<GroupBuf> gb;
+    std::vector<void *> dev;           // device allocations
+    std::vector<hipStream_t> streams;  // fork streams of the persistent launch
+    std::vector<hipEvent_t> events;
+    hipStream_t cap = nullptr;
+    hipGraphExec_t exec = nullptr;
+
+    hipError_t alloc(void **p, size_t bytes)
+    {
+        hipError_t e = hipMalloc(p, bytes);
+        if (e == hipSuccess) dev.push_back(*p);
+        return e;
+    }
+    void release()
+    {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        for (hipEvent_t e : events) (void)hipEventDestroy(e);
+        for (hipStream_t s : streams) (void)hipStreamDestroy(s);
+        if (cap) (void)hipStreamDestroy(cap);
+        for (void *p : dev) (void)hipFree(p);
+        exec = nullptr;
+        events.clear();
+        streams.clear();
+        cap = nullptr;
+        dev.clear();
+    }
+};
+
+// Relative cost of a point-level (for splitting the persistent grid between groups).
+double level_weight(int scheme) { return scheme == SW_EULER ? 20.0 : (scheme == SW_KS ? 2.0 : 1.0); }
+
+// Capture the phase-index launches of every group (one launch per phase index and
+// group, timing stamps after each phase index).
+int capture_lockstep(EnsembleRun &run, uint64_t *d_stamps, int max_phases, hipGraph_t *graph)
+{
+    BHIP(hipStreamBeginCapture(run.cap, hipStreamCaptureModeThreadLocal));
+    hipError_t le = launch_stamp(d_stamps, 0, run.cap);
+    for (int p = 0; p < max_phases && le == hipSuccess; ++p) {
+        for (GroupBuf &g : run.gb) {
+            // solves still running at phase p: a prefix of the sorted group
+            size_t a = 0;
+            while (a < g.desc.size() && g.desc[a].nphases > p) ++a;
+            const int64_t nitems = g.prefix[a];
+            if (nitems == 0) continue;
+            const int grid = (int)std::min<int64_t>(nitems, g.grid_cap);
+            le = launch_batch_phase(g.scheme, g.P, g.d_desc, g.d_items, nitems, p, grid, run.cap);
+            if (le != hipSuccess) break;
+        }
+        if (le == hipSuccess) le = launch_stamp(d_stamps, p + 1, run.cap);
+    }
+    hipError_t ce = hipStreamEndCapture(run.cap, graph);
+    if (le != hipSuccess) return hip_fail(le, "batched phase launch");
+    if (ce != hipSuccess) return hip_fail(ce, "hipStreamEndCapture");
+    return SW_OK;
+}
+
+// Per-group device state of the persistent launch.
+struct PersistGroup {
+    PersistArgs q{};
+    int grid = 1;
+    int64_t nsolves = 0;
+    std::vector<int64_t> phase_start;
+};
+
+// Capture one persistent launch per group, the groups on parallel branches of the graph
+// (each with its share of the resident work-groups), after a stamp of the start time.
+int capture_persistent(EnsembleRun &run, std::vector<PersistGroup> &pg, uint64_t *d_t0, hipGraph_t *graph)
+{
+    BHIP(hipStreamBeginCapture(run.cap, hipStreamCaptureModeThreadLocal));
+    hipError_t le = launch_stamp(d_t0, 0, run.cap);
+    hipEvent_t fork = run.events[0];
+    if (le == hipSuccess) le = hipEventRecord(fork, run.cap);
+    for (size_t g = 0; g < pg.size() && le == hipSuccess; ++g) {
+        hipStream_t s = run.streams[g];
+        hipEvent_t join = run.events[g + 1];
+        const PersistArgs &q = pg[g].q;
+        const int64_t items = pg[g].phase_start.empty() ? 0 : (int64_t)run.gb[g].items.size();
+        if ((le = hipStreamWaitEvent(s, fork, 0)) != hipSuccess) break;
+        // counters start at zero (a fill kernel, not a memset node, inside a graph)
+        if ((le = launch_zero_words(q.done, items, s)) != hipSuccess) break;
+        if ((le = launch_zero_words(q.finished, pg[g].nsolves, s)) != hipSuccess) break;
+        if ((le = launch_zero_words(q.next, 2, s)) != hipSuccess) break;
+        if ((le = launch_zero_words(q.error, 1, s)) != hipSuccess) break;
+        if ((le = launch_persistent_batch(run.gb[g].scheme, run.gb[g].P, q, pg[g].grid, s)) != hipSuccess) break;
+        if ((le = hipEventRecord(join, s)) != hipSuccess) break;
+        le = hipStreamWaitEvent(run.cap, join, 0);
+    }
+    hipError_t ce = hipStreamEndCapture(run.cap, graph);
+    if (le != hipSuccess) return hip_fail(le, "persistent batched launch");
+    if (ce != hipSuccess) return hip_fail(ce, "hipStreamEndCapture");
+    return SW_OK;
+}
+
+// Run a set of admitted swept tickets to completion as one graph (ensemble mode):
+// one launch per phase index and group, or (SW_BATCH_PERSISTENT) one persistent
+// launch per group.  Every exit goes through one cleanup: device buffers freed,
+// edges returned to the arena, tickets DONE or FAILED.
 int run_ensemble(sw_batch *b, std::vector<Ticket *> &ts, hipStream_t st)
 {
-    // allocate edges
+    EnsembleRun run;
+    int rc = SW_OK;
+    const bool persistent = (b->cfg.flags & SW_BATCH_PERSISTENT) != 0;
+    std::vector<PersistGroup> pg;
+    uint64_t *d_stamps = nullptr;   // lock-step: per phase index; persistent: [0] = start
+    std::vector<uint64_t> stamps;
+    int max_phases = 0, clock_khz = 0;
+    double t0 = 0.0;
+    auto finish = [&](int code) {
+        if (code == SW_OK) {
+            const double tick_s = clock_khz > 0 ? 1.0 / (1000.0 * clock_khz) : 0.0;
+            size_t k = 0;
+            for (size_t g = 0; g < run.gb.size(); ++g)
+                for (size_t i = 0; i < run.gb[g].members.size(); ++i, ++k) {
+                    Ticket *t = run.gb[g].members[i];
+                    const uint64_t end = persistent ? stamps[1 + k] : stamps[(size_t)phase_count(t->geom.Q, t->geom.rem)];
+                    t->t_end = t0 + (double)(end - stamps[0]) * tick_s;
+                    t->status = SW_TICKET_DONE;
+                }
+        } else {
+            const double t = now_s();
+            for (Ticket *x : ts) { x->status = SW_TICKET_FAILED; x->t_end = t; }
+        }
+        run.release();
+        for (Ticket *t : ts) {
+            b->arena.release(t->edges, (size_t)t->geom.edge_doubles * sizeof(double));
+            t->edges = nullptr;
+            release_events(t);
+        }
+        return code;
+    };
     for (Ticket *t : ts) {
-        t->edges = (double *)b->arena.alloc((size_t)t->geom.edge_doubles * sizeof(double));
-        if (!t->edges) return fail(SW_ENOMEM, "edge arena allocation failed");
         t->phase = 0;
+        t->edges = (double *)b->arena.alloc((size_t)t->geom.edge_doubles * sizeof(double));
+        if (!t->edges) return finish(fail(SW_ENOMEM, "edge arena allocation failed"));
     }
     // group by (scheme, P), sort by phase count (descending)
     std::map<std::pair<int, int>, std::vector<Ticket *>> groups;
     for (Ticket *t : ts) groups[{t->prob.scheme, t->P}].push_back(t);
-    std::vector<GroupBuf> gb;
-    int max_phases = 0;
     for (auto &kv : groups) {
         auto &v = kv.second;
         std::stable_sort(v.begin(), v.end(), [](const Ticket *x, const Ticket *y) {
@@ -242,6 +399,7 @@ int run_ensemble(sw_batch *b, std::vector<Ticket *> &ts, hipStream_t st)
         GroupBuf g;
         g.scheme = kv.first.first;
         g.P = kv.first.second;
+        g.members = v;
         g.prefix.push_back(0);
         for (size_t s = 0; s < v.size(); ++s) {
             g.desc.push_back(make_desc(*v[s]));
@@ -250,82 +408,112 @@ int run_ensemble(sw_batch *b, std::vector<Ticket *> &ts, hipStream_t st)
             max_phases = std::max(max_phases, g.desc.back().nphases);
         }
         g.grid_cap = batch_blocks_per_cu(g.scheme, g.P) * num_cus();
-        gb.push_back(std::move(g));
+        run.gb.push_back(std::move(g));
     }
-    int rc = SW_OK;
-    // device wall-clock stamps: stamps[0] before the first phase, stamps[p+1] after phase p
-    uint64_t *d_stamps = nullptr;
-    std::vector<uint64_t> stamps((size_t)max_phases + 1, 0);
-    BHIP(hipMalloc(&d_stamps, stamps.size() * sizeof(uint64_t)));
-    int clock_khz = 0;
     {
         int dev = 0;
-        BHIP(hipGetDevice(&dev));
-        BHIP(hipDeviceGetAttribute(&clock_khz, hipDeviceAttributeWallClockRate, dev));
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&clock_khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess)
+            return finish(fail(SW_EDEVICE, "device clock rate"));
     }
-    for (GroupBuf &g : gb) {
-        BHIP(hipMalloc(&g.d_desc, g.desc.size() * sizeof(SolveDesc)));
-        BHIP(hipMalloc(&g.d_items, g.items.size() * sizeof(int2)));
-        BHIP(hipMemcpyAsync(g.d_desc, g.desc.data(), g.desc.size() * sizeof(SolveDesc), hipMemcpyHostToDevice, st));
-        BHIP(hipMemcpyAsync(g.d_items, g.items.data(), g.items.size() * sizeof(int2), hipMemcpyHostToDevice, st));
+    const size_t nstamps = persistent ? 1 + ts.size() : (size_t)max_phases + 1;
+    stamps.assign(nstamps, 0);
+    if (run.alloc((void **)&d_stamps, nstamps * sizeof(uint64_t)) != hipSuccess)
+        return finish(fail(SW_ENOMEM, "stamp buffer allocation failed"));
+    for (GroupBuf &g : run.gb) {
+        if (run.alloc((void **)&g.d_desc, g.desc.size() * sizeof(SolveDesc)) != hipSuccess ||
+            run.alloc((void **)&g.d_items, g.items.size() * sizeof(int2)) != hipSuccess)
+            return finish(fail(SW_ENOMEM, "batch table allocation failed"));
+        if (hipMemcpyAsync(g.d_desc, g.desc.data(), g.desc.size() * sizeof(SolveDesc), hipMemcpyHostToDevice, st) != hipSuccess ||
+            hipMemcpyAsync(g.d_items, g.items.data(), g.items.size() * sizeof(int2), hipMemcpyHostToDevice, st) != hipSuccess)
+            return finish(fail(SW_EDEVICE, "batch table upload"));
     }
-    BHIP(hipStreamSynchronize(st));
-
-    // capture every phase launch of every group into one graph
-    hipStream_t cap = nullptr;
-    BHIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-    BHIP(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
-    hipError_t le = launch_stamp(d_stamps, 0, cap);
-    for (int p = 0; p < max_phases && le == hipSuccess; ++p) {
-        for (GroupBuf &g : gb) {
-            // solves still running at phase p: a prefix of the sorted group
-            size_t a = 0;
-            while (a < g.desc.size() && g.desc[a].nphases > p) ++a;
-            const int64_t nitems = g.prefix[a];
-            if (nitems == 0) continue;
-            const int grid = (int)std::min<int64_t>(nitems, g.grid_cap);
-            le = launch_batch_phase(g.scheme, g.P, g.d_desc, g.d_items, nitems, p, grid, cap);
-            if (le != hipSuccess) break;
+    if (persistent) {
+        // queue layout, counters, and each group's share of the resident work-groups
+        double total_work = 0.0;
+        std::vector<double> work(run.gb.size(), 0.0);
+        for (size_t g = 0; g < run.gb.size(); ++g) {
+            for (const Ticket *t : run.gb[g].members)
+                work[g] += (double)t->geom.n * (double)t->geom.levels * level_weight(t->prob.scheme);
+            total_work += work[g];
         }
-        if (le == hipSuccess) le = launch_stamp(d_stamps, p + 1, cap);
+        pg.resize(run.gb.size());
+        size_t stamp_off = 1;
+        for (size_t g = 0; g < run.gb.size(); ++g) {
+            GroupBuf &gb = run.gb[g];
+            PersistGroup &x = pg[g];
+            int gp = gb.desc.empty() ? 0 : gb.desc.front().nphases;   // sorted: the largest first
+            x.phase_start.assign((size_t)gp + 1, 0);
+            size_t a = gb.desc.size();
+            for (int p = 0; p < gp; ++p) {
+                while (a > 0 && gb.desc[a - 1].nphases <= p) --a;
+                x.phase_start[(size_t)p + 1] = x.phase_start[(size_t)p] + gb.prefix[a];
+            }
+            x.nsolves = (int64_t)gb.desc.size();
+            int64_t *d_ps = nullptr;
+            int32_t *d_done = nullptr, *d_fin = nullptr, *d_err = nullptr;
+            unsigned long long *d_next = nullptr;
+            if (run.alloc((void **)&d_ps, x.phase_start.size() * sizeof(int64_t)) != hipSuccess ||
+                run.alloc((void **)&d_done, std::max<size_t>(gb.items.size(), 1) * sizeof(int32_t)) != hipSuccess ||
+                run.alloc((void **)&d_fin, std::max<size_t>(gb.desc.size(), 1) * sizeof(int32_t)) != hipSuccess ||
+                run.alloc((void **)&d_next, sizeof(unsigned long long)) != hipSuccess ||
+                run.alloc((void **)&d_err, sizeof(int32_t)) != hipSuccess)
+                return finish(fail(SW_ENOMEM, "persistent batch allocation failed"));
+            if (hipMemcpyAsync(d_ps, x.phase_start.data(), x.phase_start.size() * sizeof(int64_t),
+                               hipMemcpyHostToDevice, st) != hipSuccess)
+                return finish(fail(SW_EDEVICE, "persistent queue upload"));
+            x.q.desc = gb.d_desc;
+            x.q.items = gb.d_items;
+            x.q.phase_start = d_ps;
+            x.q.done = d_done;
+            x.q.finished = d_fin;
+            x.q.stamps = d_stamps + stamp_off;
+            x.q.next = d_next;
+            x.q.error = d_err;
+            x.q.max_phases = gp;
+            x.q.spin_limit = (int64_t)1 << 22;   // a few seconds of polling
+            stamp_off += gb.desc.size();
+            const int occ = persistent_blocks_per_cu(gb.scheme, gb.P) * num_cus();
+            const double share = total_work > 0.0 ? work[g] / total_work : 1.0;
+            x.grid = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)(occ * share + 0.5),
+                                                                 std::max<int64_t>(x.phase_start.back(), 1)));
+        }
+        run.streams.assign(run.gb.size(), nullptr);
+        run.events.assign(run.gb.size() + 1, nullptr);
+        for (hipStream_t &s : run.streams)
+            if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) { s = nullptr; return finish(fail(SW_EDEVICE, "stream creation")); }
+        for (hipEvent_t &e : run.events)
+            if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) { e = nullptr; return finish(fail(SW_EDEVICE, "event creation")); }
     }
-    hipError_t ce = hipStreamEndCapture(cap, &graph);
-    if (le != hipSuccess) rc = hip_fail(le, "batched phase launch");
-    else if (ce != hipSuccess) rc = hip_fail(ce, "hipStreamEndCapture");
+    if (hipStreamSynchronize(st) != hipSuccess) return finish(fail(SW_EDEVICE, "batch table upload"));
+    if (hipStreamCreateWithFlags(&run.cap, hipStreamNonBlocking) != hipSuccess) {
+        run.cap = nullptr;
+        return finish(fail(SW_EDEVICE, "capture stream creation"));
+    }
+    hipGraph_t graph = nullptr;
+    rc = persistent ? capture_persistent(run, pg, d_stamps, &graph) : capture_lockstep(run, d_stamps, max_phases, &graph);
     if (rc == SW_OK) {
-        hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-        if (e != hipSuccess) rc = hip_fail(e, "hipGraphInstantiate");
+        hipError_t e = hipGraphInstantiate(&run.exec, graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) { run.exec = nullptr; rc = hip_fail(e, "hipGraphInstantiate"); }
     }
     if (graph) (void)hipGraphDestroy(graph);
-    const double t0 = now_s();
-    if (rc == SW_OK) {
-        for (Ticket *t : ts) { t->status = SW_TICKET_RUNNING; t->t_start = t0; }
-        hipError_t e = hipGraphLaunch(exec, st);
-        if (e == hipSuccess) e = hipStreamSynchronize(st);
-        if (e != hipSuccess) rc = hip_fail(e, "batched graph");
+    if (rc) return finish(rc);
+    for (Ticket *t : ts)
+        if (wait_ready(*t, st) != hipSuccess) return finish(fail(SW_EDEVICE, "waiting for the submitted states"));
+    t0 = now_s();
+    for (Ticket *t : ts) { t->status = SW_TICKET_RUNNING; t->t_start = t0; }
+    hipError_t e = hipGraphLaunch(run.exec, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return finish(hip_fail(e, "batched graph"));
+    if (hipMemcpy(stamps.data(), d_stamps, stamps.size() * sizeof(uint64_t), hipMemcpyDeviceToHost) != hipSuccess)
+        return finish(fail(SW_EDEVICE, "reading completion timestamps"));
+    for (const PersistGroup &x : pg) {
+        int32_t err = 0;
+        if (hipMemcpy(&err, x.q.error, sizeof(err), hipMemcpyDeviceToHost) != hipSuccess)
+            return finish(fail(SW_EDEVICE, "reading the persistent batch status"));
+        if (err) return finish(fail(SW_EDEVICE, "persistent batch: a dependency wait gave up"));
     }
-    // completion time of a solve = the stamp after its last phase
-    if (rc == SW_OK &&
-        hipMemcpy(stamps.data(), d_stamps, stamps.size() * sizeof(uint64_t), hipMemcpyDeviceToHost) != hipSuccess)
-        rc = fail(SW_EDEVICE, "reading phase timestamps");
-    if (rc == SW_OK) {
-        const double tick_s = clock_khz > 0 ? 1.0 / (1000.0 * clock_khz) : 0.0;
-        for (Ticket *t : ts) {
-            const int np = phase_count(t->geom.Q, t->geom.rem);
-            t->t_end = t0 + (double)(stamps[(size_t)np] - stamps[0]) * tick_s;
-            t->status = SW_TICKET_DONE;
-        }
-    } else {
-        for (Ticket *t : ts) t->status = SW_TICKET_FAILED;
-    }
-    if (exec) (void)hipGraphExecDestroy(exec);
-    (void)hipStreamDestroy(cap);
-    (void)hipFree(d_stamps);
-    for (GroupBuf &g : gb) { (void)hipFree(g.d_desc); (void)hipFree(g.d_items); }
-    for (Ticket *t : ts) { b->arena.release(t->edges, (size_t)t->geom.edge_doubles * sizeof(double)); t->edges = nullptr; }
-    return rc;
+    return finish(SW_OK);
 }
 
 // Solves no swept tile width divides: classic time-stepping through a plan.
@@ -336,7 +524,8 @@ int run_classic_ticket(Ticket &t, hipStream_t st)
     if (rc) { t.status = SW_TICKET_FAILED; return rc; }
     t.status = SW_TICKET_RUNNING;
     t.t_start = now_s();
-    rc = classic_solve(plan, t.state, st);
+    if (wait_ready(t, st) != hipSuccess) rc = fail(SW_EDEVICE, "waiting for the submitted state");
+    if (rc == SW_OK) rc = classic_solve(plan, t.state, st);
     if (rc == SW_OK && hipStreamSynchronize(st) != hipSuccess) rc = fail(SW_EDEVICE, "classic batch solve");
     swept_plan_destroy(plan);
     t.t_end = now_s();
@@ -450,8 +639,11 @@ hipError_t prepare_table(ServeGroup &g)
     for (Ticket *t : g.pending) add_i += (size_t)t->geom.K;
     const bool compact = g.dead_items * 2 > g.nitems && g.dead_items > 0;
     if (add_d == 0 && !compact) return hipSuccess;
-    for (Ticket *t : g.pending) t->admit_tick = g.enqueued;
     hipError_t e;
+    for (Ticket *t : g.pending) {
+        t->admit_tick = g.enqueued;
+        if ((e = wait_ready(*t, g.stream)) != hipSuccess) return e;   // before its first tick
+    }
     bool realloc = false;
     if (!compact && (e = g.reserve(g.ndesc + add_d, g.nitems + add_i, &realloc)) != hipSuccess) return e;
     if (!compact && !realloc) {
@@ -500,6 +692,7 @@ void retire(sw_batch *b, Ticket *t, int32_t status, double t_done)
 {
     t->status = status;
     t->t_end = t_done;
+    release_events(t);
     b->arena.release(t->edges, (size_t)t->geom.edge_doubles * sizeof(double));
     t->edges = nullptr;
     b->resident -= t->bytes;
@@ -553,6 +746,7 @@ void serve_loop(sw_batch *b)
 {
     (void)hipSetDevice(b->device);
     std::map<std::pair<int, int>, ServeGroup> groups;
+    std::vector<Ticket *> classic_running;   // classic fallbacks in flight on b->stream
     for (;;) {
         std::vector<Ticket *> classic_now;
         bool stopping = false, busy = false;
@@ -562,9 +756,17 @@ void serve_loop(sw_batch *b)
             while (!b->queue.empty()) {
                 Ticket *t = find_ticket(b, b->queue.front());
                 if (!t || t->status != SW_TICKET_QUEUED) { b->queue.pop_front(); continue; }
-                if (!t->swept) { classic_now.push_back(t); b->queue.pop_front(); continue; }
                 const bool slots_full = b->cfg.max_slots > 0 && b->nresident >= b->cfg.max_slots;
                 if (slots_full || b->resident + t->bytes > b->cfg.budget_bytes) break;
+                if (!t->swept) {   // classic fallback: admitted like the others, run beside them
+                    t->status = SW_TICKET_RUNNING;
+                    t->t_start = now_s();
+                    b->resident += t->bytes;
+                    b->nresident += 1;
+                    classic_now.push_back(t);
+                    b->queue.pop_front();
+                    continue;
+                }
                 t->edges = (double *)b->arena.alloc((size_t)t->geom.edge_doubles * sizeof(double));
                 if (!t->edges) break;  // retry when memory frees up
                 t->nphases = phase_count(t->geom.Q, t->geom.rem);
@@ -583,10 +785,36 @@ void serve_loop(sw_batch *b)
             }
             stopping = b->stop;
         }
+        // classic fallbacks run on the batch's own stream, in flight beside the groups' ticks
         for (Ticket *t : classic_now) {
-            (void)run_classic_ticket(*t, b->stream);
+            int rc = swept_plan(&t->prob, nullptr, &t->plan);
+            if (rc == SW_OK && wait_ready(*t, b->stream) != hipSuccess) rc = SW_EDEVICE;
+            if (rc == SW_OK) rc = classic_solve(t->plan, t->state, b->stream);
+            if (rc == SW_OK && (hipEventCreateWithFlags(&t->finished, hipEventDisableTiming) != hipSuccess ||
+                                hipEventRecord(t->finished, b->stream) != hipSuccess))
+                rc = SW_EDEVICE;
             std::lock_guard<std::mutex> lk(b->mu);
+            if (rc == SW_OK) {
+                classic_running.push_back(t);
+            } else {
+                (void)hipStreamSynchronize(b->stream);
+                swept_plan_destroy(t->plan);
+                t->plan = nullptr;
+                retire(b, t, SW_TICKET_FAILED, now_s());
+                b->cv.notify_all();
+            }
+        }
+        for (size_t k = 0; k < classic_running.size();) {
+            Ticket *t = classic_running[k];
+            const hipError_t q = hipEventQuery(t->finished);
+            if (q == hipErrorNotReady) { ++k; continue; }
+            swept_plan_destroy(t->plan);
+            t->plan = nullptr;
+            std::lock_guard<std::mutex> lk(b->mu);
+            retire(b, t, q == hipSuccess ? SW_TICKET_DONE : SW_TICKET_FAILED, now_s());
             b->cv.notify_all();
+            classic_running.erase(classic_running.begin() + (long)k);
+            classic_now.push_back(t);   // counts as progress
         }
         bool progressed = !classic_now.empty();
         for (auto &kv : groups) {
@@ -610,6 +838,7 @@ void serve_loop(sw_batch *b)
             }
             if (!g.inflight.empty() || g.active > 0) busy = true;
         }
+        if (!classic_running.empty()) busy = true;
         if (!busy) {
             std::unique_lock<std::mutex> lk(b->mu);
             if (b->queue.empty() && (stopping || b->stop)) break;
@@ -654,8 +883,13 @@ extern "C" {
 int batch_create(const sw_batch_config *config, sw_batch **out)
 {
     if (!config || !out) return fail(SW_EINVAL, "NULL argument");
-    if (config->budget_bytes <= 0 || config->max_slots < 0 || (config->flags & ~SW_BATCH_SERVE) != 0)
+    if (config->budget_bytes <= 0 || config->max_slots < 0 ||
+        (config->flags & ~(SW_BATCH_SERVE | SW_BATCH_PERSISTENT)) != 0 || config->reserved != 0 ||
+        ((config->flags & SW_BATCH_SERVE) && (config->flags & SW_BATCH_PERSISTENT)))
         return fail(SW_EINVAL, "invalid batch configuration");
+    const int ppl = config->points_per_lane;
+    if (ppl != 0 && ppl != 1 && ppl != 2 && ppl != 4 && ppl != 8)
+        return fail(SW_EINVAL, "points_per_lane must be 0, 1, 2, 4 or 8");
     sw_batch *b = new (std::nothrow) sw_batch();
     if (!b) return fail(SW_ENOMEM, "batch allocation failed");
     b->cfg = *config;
@@ -668,23 +902,37 @@ int batch_create(const sw_batch_config *config, sw_batch **out)
     return SW_OK;
 }
 
-int batch_submit(sw_batch *b, const sw_problem *problem, double *d_state, uint64_t *ticket)
+namespace {
+
+int submit_ticket(sw_batch *b, const sw_problem *problem, double *d_state, hipStream_t *ready_on,
+                  uint64_t *ticket)
 {
     if (!b || !ticket) return fail(SW_EINVAL, "NULL argument");
     std::string err;
     int rc = validate_problem(problem, &err);
     if (rc) return fail(rc, err);
     if ((rc = check_device_ptr(d_state))) return rc;
-    const int64_t bytes = resident_bytes(*problem);
-    if (bytes > b->cfg.budget_bytes) return fail(SW_EBUSY, "solve larger than the batch memory budget");
-    std::lock_guard<std::mutex> lk(b->mu);
     Ticket t;
+    t.swept = batch_shape(*problem, b->cfg.points_per_lane, &t.P, &t.geom) && problem->nsteps > 0;
+    const int64_t bytes = resident_bytes(*problem, t.swept, t.geom);
+    if (bytes > b->cfg.budget_bytes) return fail(SW_EBUSY, "solve larger than the batch memory budget");
+    if (ready_on) {
+        // the solve's first launch waits for the work the caller has queued on its stream
+        if (hipEventCreateWithFlags(&t.ready, hipEventDisableTiming) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(SW_EDEVICE, "event creation failed");
+        }
+        if (hipEventRecord(t.ready, *ready_on) != hipSuccess) {
+            (void)hipEventDestroy(t.ready);
+            return fail(SW_EDEVICE, "recording the submitting stream failed");
+        }
+    }
+    std::lock_guard<std::mutex> lk(b->mu);
     t.id = b->next_id++;
     t.prob = *problem;
     t.state = d_state;
     t.bytes = bytes;
     t.t_submit = now_s();
-    t.swept = batch_shape(*problem, &t.P, &t.geom) && problem->nsteps > 0;
     b->tickets.push_back(t);
     *ticket = t.id;
     if (b->serve) {
@@ -692,6 +940,20 @@ int batch_submit(sw_batch *b, const sw_problem *problem, double *d_state, uint64
         b->cv.notify_all();
     }
     return SW_OK;
+}
+
+}  // namespace
+
+int batch_submit(sw_batch *b, const sw_problem *problem, double *d_state, uint64_t *ticket)
+{
+    return submit_ticket(b, problem, d_state, nullptr, ticket);
+}
+
+int batch_submit_async(sw_batch *b, const sw_problem *problem, double *d_state, void *hip_stream,
+                       uint64_t *ticket)
+{
+    hipStream_t st = (hipStream_t)hip_stream;
+    return submit_ticket(b, problem, d_state, &st, ticket);
 }
 
 int batch_run(sw_batch *b, void *hip_stream)
@@ -712,6 +974,7 @@ int batch_run(sw_batch *b, void *hip_stream)
             if (!t.swept) {
                 if (t.prob.nsteps == 0) { t.status = SW_TICKET_DONE; t.t_start = t.t_end = now_s(); continue; }
                 int rc = run_classic_ticket(t, st);
+                release_events(&t);
                 if (rc && rc_all == SW_OK) rc_all = rc;
                 continue;
             }
@@ -753,6 +1016,7 @@ int batch_ticket_info(sw_batch *b, uint64_t ticket, sw_ticket_info *out)
     i.submit_s = t->t_submit;
     i.start_s = t->t_start;
     i.end_s = t->t_end;
+    i.resident_bytes = t->bytes;
     *out = i;
     return SW_OK;
 }
@@ -797,6 +1061,7 @@ void batch_destroy(sw_batch *b)
     if (b->serve) serve_stop(b);
     {
         std::lock_guard<std::mutex> lk(b->mu);
+        for (Ticket &t : b->tickets) release_events(&t);
         b->arena.destroy();
     }
     delete b;

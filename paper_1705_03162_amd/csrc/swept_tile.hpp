@@ -431,9 +431,25 @@ __device__ __forceinline__ void wave_widen(const TileArgs &a, int lane, double *
     }
 }
 
+// Global loads and stores of a tile's rows.  COH: coherent at agent scope (relaxed
+// agent-scope atomics, which bypass the XCD-private caches' stale copies), for tiles
+// whose inputs another XCD may have just written within the same launch.
+template <bool COH>
+__device__ __forceinline__ double gload(const double *p)
+{
+    if constexpr (COH) return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else return *p;
+}
+template <bool COH>
+__device__ __forceinline__ void gstore(double *p, double v)
+{
+    if constexpr (COH) __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else *p = v;
+}
+
 // One tile of one phase on a one-wave work-group.  `stage` holds 2 NV wave_span(P0)
 // doubles of LDS: both rows of the tile.
-template <class Sch, int P0>
+template <class Sch, int P0, bool COH = false>
 __device__ __forceinline__ void wave_tile(const TileArgs &args, int64_t j, int lane, double *stage)
 {
     constexpr int NV = Sch::NV, R = Sch::R, SPAN = wave_span(P0);
@@ -449,7 +465,7 @@ __device__ __forceinline__ void wave_tile(const TileArgs &args, int64_t j, int l
             const int x = 64 * i + lane;
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
-                stage[(2 * v + 0) * SPAN + lds_pos(x)] = a.state[(int64_t)v * a.n + g0 + x];
+                stage[(2 * v + 0) * SPAN + lds_pos(x)] = gload<COH>(a.state + (int64_t)v * a.n + g0 + x);
                 stage[(2 * v + 1) * SPAN + lds_pos(x)] = 0.0;
             }
         }
@@ -469,16 +485,16 @@ __device__ __forceinline__ void wave_tile(const TileArgs &args, int64_t j, int l
             const double *src = x < half ? sa + x + R : sb + x - half;
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
-                stage[(2 * v + 0) * SPAN + lds_pos(x)] = src[(v * 2 + 0) * a.E];
-                stage[(2 * v + 1) * SPAN + lds_pos(x)] = src[(v * 2 + 1) * a.E];
+                stage[(2 * v + 0) * SPAN + lds_pos(x)] = gload<COH>(src + (v * 2 + 0) * a.E);
+                stage[(2 * v + 1) * SPAN + lds_pos(x)] = gload<COH>(src + (v * 2 + 1) * a.E);
             }
         }
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
 #pragma unroll
             for (int i = 0; i < R; ++i) {
-                hl[v][i] = sa[(v * 2 + 1) * a.E + i];
-                hr[v][i] = sb[(v * 2 + 1) * a.E + half + i];
+                hl[v][i] = gload<COH>(sa + (v * 2 + 1) * a.E + i);
+                hr[v][i] = gload<COH>(sb + (v * 2 + 1) * a.E + half + i);
             }
         }
         if (a.bc == BC_DIRICHLET && a.offset == 0) {   // the unshifted tiles at the walls
@@ -503,7 +519,8 @@ __device__ __forceinline__ void wave_tile(const TileArgs &args, int64_t j, int l
         if (wall) wave_widen<Sch, min_class(P0), P0, true>(a, lane, stage, 1, top, n_last, hl, hr);
         else wave_widen<Sch, min_class(P0), P0, false>(a, lane, stage, 1, top, n_last, hl, hr);
     }
-    // every class parked its rows: the stage holds both final rows of the whole tile
+    // every class parked its rows: the stage holds both final rows of the whole tile;
+    // new L slot into a (points [0, w/2 + r)), new R slot into b (points [w/2 - r, w))
     if (a.kind != PH_DOWN) {
         double *sa = a.edges + slot_base<Sch>(a, slot_a(a, j));
         double *sb = a.edges + slot_base<Sch>(a, slot_b(a, j));
@@ -512,8 +529,12 @@ __device__ __forceinline__ void wave_tile(const TileArgs &args, int64_t j, int l
             const int x = 64 * i + lane;
 #pragma unroll
             for (int v = 0; v < NV; ++v)
-                store_edge_point<Sch>(a, sa, sb, v, x, stage[(2 * v + 0) * SPAN + lds_pos(x)],
-                                      stage[(2 * v + 1) * SPAN + lds_pos(x)]);
+#pragma unroll
+                for (int q = 0; q < 2; ++q) {
+                    const double val = stage[(2 * v + q) * SPAN + lds_pos(x)];
+                    if (x < half + R) gstore<COH>(sa + (v * 2 + q) * a.E + x, val);
+                    if (x >= half - R) gstore<COH>(sb + (v * 2 + q) * a.E + x - (half - R), val);
+                }
         }
     }
     int lo, hi;
@@ -526,8 +547,8 @@ __device__ __forceinline__ void wave_tile(const TileArgs &args, int64_t j, int l
         if (x >= lo && x < hi) {
 #pragma unroll
             for (int v = 0; v < NV; ++v)
-                store_top_point<Sch>(a, g0, topl, v, x, stage[(2 * v + 0) * SPAN + lds_pos(x)],
-                                     stage[(2 * v + 1) * SPAN + lds_pos(x)]);
+                gstore<COH>(a.state + (int64_t)v * a.n + wrap_once(g0 + x, a.n),
+                            stage[(2 * v + (topl & 1)) * SPAN + lds_pos(x)]);
         }
     }
 }
@@ -596,18 +617,22 @@ __global__ __launch_bounds__(64) void batch_tiles(const SolveDesc *__restrict__ 
     }
 }
 
+constexpr int kPersistChunk = 4;   // queue entries taken per counter update
+
 // Persistent batched launch (ensemble): one-wave work-groups take entries from one
 // counter in phase-major order -- every (solve, tile) of phase 0, then of phase 1,
 // ... -- and run each as soon as the tiles of the previous phase whose outputs it
 // reads (phase_deps) are done: no launch per phase and no grid-wide barrier, the
 // GPU-side synchronisation the paper's Conclusions suggest in place of kernel
-// launches.  Completion counters are published with agent-scope release and read
-// with agent-scope acquire, which writes back and invalidates the XCD-private L2
-// caches as needed.  Entry i of phase p is items[i - phase_start[p]]; its tile's
+// launches.  The eight XCDs' L2 caches are not coherent with each other, so every
+// global access of these tiles is a relaxed agent-scope atomic (coherent at the device
+// level, no whole-cache write-back or invalidation), and a tile publishes its
+// completion counter only after all its stores have completed; a dependent tile
+// issues its loads only after it has read that counter.  Entry i of phase p is items[i - phase_start[p]]; its tile's
 // counter is done[i - phase_start[p]].  Phase-major order makes every dependency an
 // earlier entry, so the work-group holding the earliest unfinished entry can always
 // proceed; a wait that runs past spin_limit polls (never in a correct run) sets
-// *error and gives up instead of hanging.
+// *error, and every wait gives up once *error is set, so the launch always ends.
 template <class Sch, int P>
 __global__ __launch_bounds__(64) void batch_persistent(PersistArgs q)
 {
@@ -615,55 +640,59 @@ __global__ __launch_bounds__(64) void batch_persistent(PersistArgs q)
     __shared__ unsigned long long entry;
     const int lane = (int)threadIdx.x;
     const int64_t total = q.phase_start[q.max_phases];
+    int p = 0;   // a work-group's entries only increase, so its phase only moves forward
     for (;;) {
-        if (lane == 0) entry = atomicAdd(q.next, 1ull);
+        // a chunk of consecutive entries per counter update
+        if (lane == 0) entry = atomicAdd(q.next, (unsigned long long)kPersistChunk);
         __syncthreads();
-        const int64_t i = (int64_t)entry;
-        __syncthreads();   // every lane has read `entry` before lane 0 takes the next one
-        if (i >= total) break;
-        int lo = 0, hi = q.max_phases;   // phase_start[lo] <= i < phase_start[hi]
-        while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (q.phase_start[mid] <= i) lo = mid;
-            else hi = mid;
-        }
-        const int p = lo;
-        const int64_t r = i - q.phase_start[p];
-        const int2 it = q.items[r];
-        const SolveDesc &d = q.desc[it.x];
-        const int64_t base = r - it.y;   // counter of the solve's tile 0
-        if (p > 0) {
-            int64_t deps[2];
-            const int nd = phase_deps(d.Q, d.rem, d.H, d.K, p, it.y, deps);
-            for (int k = 0; k < nd; ++k) {
-                int64_t spins = 0;
-                while (__hip_atomic_load(q.done + base + deps[k], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < p) {
-                    if (++spins > q.spin_limit) {
-                        if (lane == 0) atomicOr(q.error, 1);
-                        break;
+        const int64_t i0 = (int64_t)entry;
+        __syncthreads();   // every lane has read `entry` before lane 0 takes the next chunk
+        if (i0 >= total) break;
+        const int64_t i1 = i0 + kPersistChunk < total ? i0 + kPersistChunk : total;
+        for (int64_t i = i0; i < i1; ++i) {
+            while (q.phase_start[p + 1] <= i) ++p;
+            const int64_t r = i - q.phase_start[p];
+            const int2 it = q.items[r];
+            const SolveDesc &d = q.desc[it.x];
+            const int64_t base = r - it.y;   // counter of the solve's tile 0
+            if (p > 0) {
+                // poll the counters with coherent loads; the tile's own loads are issued after
+                int64_t deps[2];
+                const int nd = phase_deps(d.Q, d.rem, d.H, d.K, p, it.y, deps);
+                for (int k = 0; k < nd; ++k) {
+                    int64_t spins = 0;
+                    while (__hip_atomic_load(q.done + base + deps[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < p) {
+                        if (++spins > q.spin_limit ||
+                            __hip_atomic_load(q.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+                            if (lane == 0) atomicOr(q.error, 1);   // every later wait gives up at once
+                            break;
+                        }
+                        __builtin_amdgcn_s_sleep(2);
                     }
-                    __builtin_amdgcn_s_sleep(2);
                 }
             }
-        }
-        TileArgs a;
-        a.state = d.state;
-        a.edges = d.edges;
-        a.n = d.n;
-        a.K = d.K;
-        a.w = d.w;
-        a.H = d.H;
-        a.E = d.E;
-        a.bc = d.bc;
-        a.ends = 0;
-        a.c = d.c;
-        phase_at(d.Q, d.rem, d.H, p, a.kind, a.levels, a.offset);
-        wave_tile<Sch, P>(a, (int64_t)it.y, lane, stage);
-        if (lane == 0) {
-            // the release orders every store of this one-wave work-group before the counter
-            __hip_atomic_store(q.done + r, p + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-            if (p + 1 == d.nphases && atomicAdd(q.finished + it.x, 1) + 1 == d.K)
-                q.stamps[it.x] = wall_clock64();   // the solve's last tile is done
+            TileArgs a;
+            a.state = d.state;
+            a.edges = d.edges;
+            a.n = d.n;
+            a.K = d.K;
+            a.w = d.w;
+            a.H = d.H;
+            a.E = d.E;
+            a.bc = d.bc;
+            a.ends = 0;
+            a.c = d.c;
+            phase_at(d.Q, d.rem, d.H, p, a.kind, a.levels, a.offset);
+            wave_tile<Sch, P, true>(a, (int64_t)it.y, lane, stage);
+            // every coherent store of this one-wave work-group has completed before the
+            // counter is published (the wave's memory counter covers all its lanes)
+            __builtin_amdgcn_s_waitcnt(0);
+            __atomic_signal_fence(__ATOMIC_SEQ_CST);
+            if (lane == 0) {
+                __hip_atomic_store(q.done + r, p + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (p + 1 == d.nphases && atomicAdd(q.finished + it.x, 1) + 1 == d.K)
+                    q.stamps[it.x] = wall_clock64();   // the solve's last tile is done
+            }
         }
     }
 }

@@ -18,6 +18,7 @@ namespace {
 std::once_flag g_once;
 std::map<std::pair<int, int>, std::pair<int, int>> g_table;
 std::map<std::pair<int, int>, int> g_classic;
+std::map<std::pair<int, int>, int> g_batch;
 
 std::string table_path()
 {
@@ -42,6 +43,8 @@ void load()
         int scheme, lg, width, threads;
         if (std::sscanf(line, "classic %d %d %d", &scheme, &lg, &threads) == 3)
             g_classic[{scheme, lg}] = threads;
+        else if (std::sscanf(line, "batch %d %d %d", &scheme, &lg, &width) == 3)
+            g_batch[{scheme, lg}] = width;   // points per lane
         else if (std::sscanf(line, "%d %d %d %d", &scheme, &lg, &width, &threads) == 4)
             g_table[{scheme, lg}] = {width, threads};
     }
@@ -66,6 +69,18 @@ bool tuned_classic_threads(const sw_problem &p, int *threads)
     for (int c = lg + 1; c <= 62 && it == g_classic.end(); ++c) it = g_classic.find({p.scheme, c});
     if (it == g_classic.end() || !legal_threads(it->second)) return false;
     *threads = it->second;
+    return true;
+}
+
+bool tuned_batch_points(const sw_problem &p, int *points)
+{
+    std::call_once(g_once, load);
+    const int lg = size_class(p.n);
+    auto it = g_batch.end();
+    for (int c = lg; c >= 0 && it == g_batch.end(); --c) it = g_batch.find({p.scheme, c});
+    for (int c = lg + 1; c <= 62 && it == g_batch.end(); ++c) it = g_batch.find({p.scheme, c});
+    if (it == g_batch.end()) return false;
+    *points = it->second;
     return true;
 }
 

@@ -42,8 +42,12 @@ struct Stream {
     uint64_t issued = 0, executed = 0;
     bool capturing = false;
     std::vector<Work> captured;
+    Stream *capture_into = nullptr;    // joined another stream's capture (fork by event)
+    std::vector<Stream *> joined;      // streams that joined this stream's capture
 };
-struct Event { Stream *stream = nullptr; uint64_t ticket = 0; };
+// An event recorded during a capture only orders captured work; the stand-in
+// graph runs its work in capture order, which is one valid order of the forks.
+struct Event { Stream *stream = nullptr; uint64_t ticket = 0; Stream *capture_origin = nullptr; };
 struct Graph { std::vector<Work> work; };
 
 inline std::recursive_mutex &lock()
@@ -71,6 +75,7 @@ inline void enqueue(Stream *s, Work w)
 {
     std::lock_guard<std::recursive_mutex> lk(lock());
     s = resolve(s);
+    if (s->capture_into) { s->capture_into->captured.push_back(std::move(w)); return; }
     if (s->capturing) { s->captured.push_back(std::move(w)); return; }
     s->queue.push_back(std::move(w));
     s->issued += 1;
@@ -126,7 +131,12 @@ inline hipError_t hipEventRecord(hipEvent_t e, hipStream_t s)
 {
     std::lock_guard<std::recursive_mutex> lk(fakehip::lock());
     s = fakehip::resolve(s);
-    if (s->capturing) return hipErrorInvalidValue;
+    if (s->capturing || s->capture_into) {
+        e->stream = nullptr;
+        e->capture_origin = s->capturing ? s : s->capture_into;
+        return hipSuccess;
+    }
+    e->capture_origin = nullptr;
     e->stream = s;
     e->ticket = s->issued;
     return hipSuccess;
@@ -144,7 +154,19 @@ inline hipError_t hipEventSynchronize(hipEvent_t e)
     if (e->stream) fakehip::run_until(e->stream, e->ticket);
     return hipSuccess;
 }
-inline hipError_t hipStreamWaitEvent(hipStream_t, hipEvent_t e, unsigned) { return hipEventSynchronize(e); }
+inline hipError_t hipStreamWaitEvent(hipStream_t s, hipEvent_t e, unsigned)
+{
+    std::lock_guard<std::recursive_mutex> lk(fakehip::lock());
+    s = fakehip::resolve(s);
+    if (e->capture_origin) {   // fork: s joins the capture; join back into the origin: nothing to do
+        if (s != e->capture_origin && !s->capture_into) {
+            s->capture_into = e->capture_origin;
+            e->capture_origin->joined.push_back(s);
+        }
+        return hipSuccess;
+    }
+    return hipEventSynchronize(e);
+}
 
 inline hipError_t hipMemcpyAsync(void *dst, const void *src, size_t bytes, hipMemcpyKind, hipStream_t s)
 {
@@ -170,6 +192,8 @@ inline hipError_t hipStreamEndCapture(hipStream_t s, hipGraph_t *g)
     *g = new fakehip::Graph{std::move(s->captured)};
     s->captured.clear();
     s->capturing = false;
+    for (fakehip::Stream *j : s->joined) j->capture_into = nullptr;
+    s->joined.clear();
     return hipSuccess;
 }
 inline hipError_t hipGraphInstantiate(hipGraphExec_t *x, hipGraph_t g, void *, char *, size_t)

@@ -27,6 +27,13 @@ def alone(prob, ic):
     return x.cpu().numpy()
 
 
+def charged_bytes(prob, x):
+    """Device bytes a batch charges this solve, read back from the library (a probe
+    batch that is never run)."""
+    with sw.Batch(budget_bytes=1 << 40) as b:
+        return b.info(b.submit(prob, x))["resident_bytes"]
+
+
 def mixed_problems(count, seed, schemes=(W.HEAT, W.KS), nmax=8192, smax=900):
     rng = np.random.default_rng(seed)
     out = []
@@ -67,13 +74,41 @@ def test_ensemble_each_result_equals_alone(oracle_mod):
         assert np.array_equal(got.reshape(prob.nvars, prob.n), oracle_mod.solve(prob, ic)), (prob.n, prob.nsteps)
 
 
+@pytest.mark.parametrize("ppl", [0, 1, 4])
+def test_persistent_ensemble_equals_oracle(oracle_mod, ppl):
+    """The persistent ensemble launch (work-groups take tiles from a device queue and wait
+    on the completion counters of the tiles they depend on): mixed heat, KS and Sod with
+    every boundary type, default and forced tile shapes; every result equals the oracle
+    bit for bit and the lock-step launch's."""
+    probs = mixed_problems(40, seed=12, schemes=(W.HEAT, W.KS, W.EULER), nmax=8192, smax=700)
+    probs.append((W.heat_problem(2048, 613, bc=W.REFLECTIVE), W.fourier_ic(2048, 7)))
+    probs.append((W.heat_problem(1024, 420, bc=W.DIRICHLET, bc_left=0.5, bc_right=-0.5),
+                  W.fourier_ic(1024, 8)))
+    probs.append((W.ks_problem(512, 3), W.fourier_ic(512, 9)))          # fewer levels than one phase
+    print(f"[gpu] persistent ensemble of {len(probs)} solves, points per lane {ppl}", flush=True)
+    runs = []
+    for persistent in (True, False):
+        states = [torch.tensor(ic, dtype=torch.float64, device=DEV) for _, ic in probs]
+        with sw.Batch(budget_bytes=1 << 34, persistent=persistent, points_per_lane=ppl) as b:
+            tickets = [b.submit(p, x) for (p, _), x in zip(probs, states)]
+            b.run()
+            assert all(b.poll(t) == N.SW_TICKET_DONE for t in tickets)
+            infos = [b.info(t) for t in tickets]
+        torch.cuda.synchronize()
+        assert all(i["end_s"] >= i["start_s"] for i in infos)
+        runs.append([x.cpu().numpy() for x in states])
+    for (prob, ic), a, b_ in zip(probs, runs[0], runs[1]):
+        assert np.array_equal(a, b_)
+        assert np.array_equal(a.reshape(prob.nvars, prob.n), oracle_mod.solve(prob, ic)), (prob.n, prob.nsteps)
+
+
 def test_ensemble_with_euler_and_budget_waves(oracle_mod):
     """Mixed ensemble in budget-limited waves; each result equals the solve alone, and the
     Sod solves (batched one-wave tiles, pressures, ratios and fluxes exchanged between
     lanes) equal the oracle bit for bit."""
     probs = mixed_problems(20, seed=2, schemes=(W.HEAT, W.KS, W.EULER), nmax=4096, smax=400)
-    budget = max(3 * p.n * p.nvars * 8 for p, _ in probs) * 3   # a few solves per wave
     states = [torch.tensor(ic, dtype=torch.float64, device=DEV) for _, ic in probs]
+    budget = max(charged_bytes(p, x) for (p, _), x in zip(probs, states)) * 3   # a few solves per wave
     with sw.Batch(budget_bytes=budget, max_slots=5) as b:
         tickets = [b.submit(p, x) for (p, _), x in zip(probs, states)]
         b.run()
@@ -141,12 +176,12 @@ def test_served_group_appends_and_compaction():
 
 def test_served_budget_never_exceeded():
     """A served batch whose budget holds only a few solves at a time: from every ticket's
-    residency interval [start, end) and its counted bytes (3 n nvars 8), the bytes resident
-    at once never exceed the budget, and every result equals the solve alone."""
+    residency interval [start, end) and the bytes the library charged it (state plus edge
+    slots, checked against the geometry), the bytes resident at once never exceed the
+    budget, and every result equals the solve alone."""
     probs = mixed_problems(24, seed=9, schemes=(W.HEAT, W.KS, W.EULER), nmax=4096, smax=500)
-    sizes = [3 * p.n * p.nvars * 8 for p, _ in probs]
-    budget = 3 * max(sizes)
     states = [torch.tensor(ic, dtype=torch.float64, device=DEV) for _, ic in probs]
+    budget = 3 * max(charged_bytes(p, x) for (p, _), x in zip(probs, states))
     torch.cuda.synchronize()
     with sw.Batch(budget_bytes=budget, serve=True) as b:
         tickets = [b.submit(p, x) for (p, _), x in zip(probs, states)]
@@ -154,6 +189,12 @@ def test_served_budget_never_exceeded():
             b.wait(t, timeout_us=60_000_000)
         infos = [b.info(t) for t in tickets]
     assert all(i["status"] == N.SW_TICKET_DONE for i in infos)
+    sizes = [i["resident_bytes"] for i in infos]            # what the library charged
+    for i, sz, (p, _) in zip(infos, sizes, probs):
+        # its state plus 2K edge slots of nvars x 2 rows x (w/2 + r) doubles, rounded to 256 B
+        w, r = i["width"], (1 if p.scheme == W.HEAT else 2)
+        edges = 2 * (p.n // w) * p.nvars * 2 * (w // 2 + r) * 8
+        assert sz == p.n * p.nvars * 8 + (edges + 255) // 256 * 256, (p.scheme, p.n)
     events = sorted([(i["start_s"], +sz) for i, sz in zip(infos, sizes)] +
                     [(i["end_s"], -sz) for i, sz in zip(infos, sizes)], key=lambda e: (e[0], e[1]))
     held = peak = 0
@@ -169,8 +210,8 @@ def test_served_budget_never_exceeded():
 def test_served_budget_queues_and_cancel():
     big = (W.ks_problem(1 << 16, 3000), W.fourier_ic(1 << 16, 1))
     small = [(W.heat_problem(1024, 200 + j), W.fourier_ic(1024, j)) for j in range(4)]
-    budget = 3 * big[0].n * 8 + 10    # the big solve alone fills the budget
     xs = [torch.tensor(ic, dtype=torch.float64, device=DEV) for _, ic in [big] + small]
+    budget = charged_bytes(big[0], xs[0]) + 10    # the big solve alone fills the budget
     with sw.Batch(budget_bytes=budget, serve=True) as b:
         tb = b.submit(big[0], xs[0])
         ts = [b.submit(p, x) for (p, _), x in zip(small, xs[1:])]

@@ -42,15 +42,24 @@ def sim():
         fn.restype, fn.argtypes = N.SIGNATURES[name]
     L.servesim_ticks.restype = ctypes.c_int64
     L.servesim_ticks.argtypes = [ctypes.c_void_p]
+    fn = L.batch_submit_async
+    fn.restype, fn.argtypes = N.SIGNATURES["batch_submit_async"]
+    L.servesim_stream_create.restype = ctypes.c_void_p
+    L.servesim_stream_create.argtypes = []
+    L.servesim_enqueue_copy.restype = None
+    L.servesim_enqueue_copy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t]
+    L.servesim_stream_destroy.restype = None
+    L.servesim_stream_destroy.argtypes = [ctypes.c_void_p]
     return L
 
 
 class SimBatch:
     """Host arrays stand in for device memory; the caller keeps them alive."""
 
-    def __init__(self, L, budget, slots=0, serve=False):
+    def __init__(self, L, budget, slots=0, serve=False, persistent=False, points_per_lane=0):
         self.L = L
-        cfg = N.SwBatchConfig(int(budget), int(slots), N.SW_BATCH_SERVE if serve else 0)
+        flags = (N.SW_BATCH_SERVE if serve else 0) | (N.SW_BATCH_PERSISTENT if persistent else 0)
+        cfg = N.SwBatchConfig(int(budget), int(slots), flags, int(points_per_lane), 0)
         h = ctypes.c_void_p()
         assert L.batch_create(ctypes.byref(cfg), ctypes.byref(h)) == 0
         self.h = h
@@ -114,7 +123,15 @@ def mixed(count, seed, schemes=(W.HEAT, W.KS, W.EULER), nmax=512, smax=120, bcs=
 
 
 def nbytes(prob):
-    return 3 * prob.n * prob.nvars * 8
+    """Device bytes the batch charges a swept solve: its state plus its edge slots
+    (2 K slots of nvars x 2 rows x (w/2 + r) doubles) rounded up to 256 bytes, for the
+    widest one-wave tile (at most 8 points per lane) that divides n."""
+    P = 8
+    while (prob.n // 64) % P:
+        P //= 2
+    w, r = 64 * P, (1 if prob.scheme == W.HEAT else 2)
+    edges = 2 * (prob.n // w) * prob.nvars * 2 * (w // 2 + r) * 8
+    return prob.n * prob.nvars * 8 + (edges + 255) // 256 * 256
 
 
 def peak_resident(infos, sizes):
@@ -136,6 +153,27 @@ def test_ensemble_equals_oracle(sim, oracle_mod):
     tickets = [b.submit(p, x) for (p, _), x in zip(probs, states)]
     assert sim.batch_run(b.h, None) == 0
     assert all(b.poll(t) == N.SW_TICKET_DONE for t in tickets)
+    b.close()
+    for (prob, ic), x in zip(probs, states):
+        assert np.array_equal(x, oracle_mod.solve(prob, ic)), (prob.scheme, prob.n, prob.nsteps, prob.bc)
+
+
+@pytest.mark.parametrize("ppl", [0, 2])
+def test_ensemble_persistent_equals_oracle(sim, oracle_mod, ppl):
+    """Persistent ensemble (one launch per tile group taking tiles from a queue in
+    phase-major order and checking the tiles it depends on): mixed schemes, sizes and
+    boundaries, default and forced tile shapes, each result equal to the oracle, and
+    every solve's charged bytes as the library reports them."""
+    probs = mixed(14, seed=24)
+    states = [ic.copy() for _, ic in probs]
+    b = SimBatch(sim, budget=1 << 30, persistent=True, points_per_lane=ppl)
+    tickets = [b.submit(p, x) for (p, _), x in zip(probs, states)]
+    assert sim.batch_run(b.h, None) == 0
+    infos = [b.info(t) for t in tickets]
+    assert all(i["status"] == N.SW_TICKET_DONE for i in infos)
+    assert all(i["end_s"] >= i["start_s"] for i in infos)
+    if ppl == 0:
+        assert [i["resident_bytes"] for i in infos] == [nbytes(p) for p, _ in probs]
     b.close()
     for (prob, ic), x in zip(probs, states):
         assert np.array_equal(x, oracle_mod.solve(prob, ic)), (prob.scheme, prob.n, prob.nsteps, prob.bc)
@@ -169,6 +207,8 @@ def test_served_equals_oracle_under_budget(sim, oracle_mod):
     b.close()
     assert all(i["status"] == N.SW_TICKET_DONE for i in infos)
     assert ticks > 0
+    # the library charges each solve its state plus its rounded edge slots
+    assert [i["resident_bytes"] for i in infos] == sizes
     assert max(sizes) < peak_resident(infos, sizes) <= budget
     for (prob, ic), x in zip(probs, snaps):
         assert np.array_equal(x, oracle_mod.solve(prob, ic)), (prob.scheme, prob.n, prob.nsteps, prob.bc)
@@ -242,3 +282,37 @@ def test_served_done_means_final(sim, oracle_mod):
     b.close()
     for (prob, ic), x in zip(probs, snaps):
         assert np.array_equal(x, oracle_mod.solve(prob, ic))
+
+
+@pytest.mark.parametrize("serve", [False, True])
+def test_async_submit_waits_for_the_submitting_stream(sim, oracle_mod, serve):
+    """batch_submit_async: the initial state is still being written by work queued on the
+    caller's stream (a copy that runs only when something waits for that stream); the
+    batch's first launch for the solve waits for it, so every result equals the oracle.
+    The same solves submitted with plain batch_submit start from the unwritten (zero)
+    state, which shows the wait is what orders them."""
+    probs = mixed(6, seed=31, schemes=(W.HEAT, W.KS))
+    for use_async in (True, False):
+        states = [np.zeros_like(ic) for _, ic in probs]
+        stream = sim.servesim_stream_create()
+        b = SimBatch(sim, budget=1 << 30, serve=serve)
+        tickets = []
+        for (p, ic), x in zip(probs, states):
+            sim.servesim_enqueue_copy(stream, x.ctypes.data, ic.ctypes.data, ic.nbytes)
+            s = N.problem_struct(p)
+            t = ctypes.c_uint64()
+            if use_async:
+                assert sim.batch_submit_async(b.h, ctypes.byref(s), x.ctypes.data, stream, ctypes.byref(t)) == 0
+            else:
+                assert sim.batch_submit(b.h, ctypes.byref(s), x.ctypes.data, ctypes.byref(t)) == 0
+            b.keep.append(s)
+            tickets.append(t.value)
+        if serve:
+            snaps = b.wait_all(tickets, states)
+        else:
+            assert sim.batch_run(b.h, None) == 0
+            snaps = [x.copy() for x in states]
+        b.close()
+        sim.servesim_stream_destroy(stream)
+        same = [np.array_equal(x, oracle_mod.solve(p, ic)) for (p, ic), x in zip(probs, snaps)]
+        assert all(same) if use_async else not any(same)
