@@ -82,12 +82,15 @@ def read_table(table: str = TABLE):
                     continue
                 if parts[0] == "classic" and len(parts) >= 4:
                     classic[(int(parts[1]), int(parts[2]))] = line.rstrip("\n")
+                elif parts[0] == "batch":
+                    continue
                 elif len(parts) >= 4:
                     swept[(int(parts[0]), int(parts[1]))] = line.rstrip("\n")
     return swept, classic
 
 
-def write_table(swept, classic, table: str = TABLE):
+def write_table(swept, classic, table: str = TABLE, batch=None):
+    batch = read_batch_rows(table) if batch is None else batch
     with open(table + ".tmp", "w") as f:
         f.write("# scheme log2n width threads  (point-updates/s, steps timed)\n")
         for k in sorted(swept):
@@ -95,6 +98,10 @@ def write_table(swept, classic, table: str = TABLE):
         f.write("# classic scheme log2n threads  (point-updates/s, steps timed)\n")
         for k in sorted(classic):
             f.write(classic[k] + "\n")
+        if batch:
+            f.write("# batch scheme log2n points-per-lane  (point-updates/s, steps timed, solves)\n")
+            for k in sorted(batch):
+                f.write(batch[k] + "\n")
     os.replace(table + ".tmp", table)
 
 
@@ -112,6 +119,66 @@ def time_classic(sw, torch, prob, ic, threads, reps):
             torch.cuda.synchronize()
             best = min(best, time.perf_counter() - t0)
     return best
+
+
+BATCH_POINTS = (1, 2, 4, 8)
+
+
+def time_batch(sw, torch, prob, ic, count, points, reps):
+    """Best seconds of running `count` copies of one problem as a batched ensemble with
+    one-wave tiles of `points` points per lane."""
+    best = float("inf")
+    x0 = torch.tensor(ic, dtype=torch.float64, device="cuda")
+    for _ in range(reps + 1):   # the first run warms up
+        xs = [x0.clone() for _ in range(count)]
+        torch.cuda.synchronize()
+        with sw.Batch(budget_bytes=64 << 30, points_per_lane=points) as b:
+            for x in xs:
+                b.submit(prob, x)
+            t0 = time.perf_counter()
+            b.run()
+            torch.cuda.synchronize()
+            best = min(best, time.perf_counter() - t0) if _ else best
+    return best
+
+
+def tune_batch(schemes=(0, 1, 2), log2ns=range(8, 19), target_s: float = 0.05, reps: int = 2,
+               table: str = TABLE, log=print):
+    """Points per lane of batched one-wave tiles per (scheme, size class): ensembles of
+    identical solves (enough to fill the GPU) timed for each legal shape, merged into the
+    table as lines "batch scheme log2n points"."""
+    import torch
+
+    import paper_1705_03162_amd as sw
+    swept, classic = read_table(table)
+    batch = read_batch_rows(table)
+    for scheme in schemes:
+        for lg in log2ns:
+            n = 1 << lg
+            count = max(8, (1 << 22) // n)
+            legal = [P for P in BATCH_POINTS if (n // 64) % P == 0 and (scheme != 2 or P <= 8)]
+            prob, ic = _problem(scheme, lg, 64)
+            t = time_batch(sw, torch, prob, ic, count, legal[-1], reps=1)
+            steps = int(min(20_000, max(64, 64 * target_s / max(t, 1e-6))))
+            prob, ic = _problem(scheme, lg, steps)
+            res = sorted((time_batch(sw, torch, prob, ic, count, P, reps), P) for P in legal)
+            t, P = res[0]
+            rate = count * n * steps / t
+            log(f"batch scheme={scheme} log2n={lg} x{count} steps={steps} best P={P} {rate:.3e} pt-upd/s; "
+                + ", ".join(f"P={pp}: {count * n * steps / x:.3e}" for x, pp in sorted(res, key=lambda r: r[1])))
+            batch[(scheme, lg)] = f"batch {scheme} {lg} {P}  # {rate:.4e} {steps} x{count}"
+    write_table(swept, classic, table, batch)
+
+
+def read_batch_rows(table: str = TABLE):
+    rows = {}
+    if os.path.exists(table):
+        with open(table) as f:
+            for line in f:
+                parts = line.split()
+                if len(parts) >= 4 and parts[0] == "batch":
+                    rows[(int(parts[1]), int(parts[2]))] = line.rstrip("\n")
+    return rows
 
 
 def tune_classic(schemes=(0, 1, 2), log2ns=range(12, 21), target_s: float = 0.02, reps: int = 3,
@@ -183,7 +250,7 @@ def main():
     ap.add_argument("--table", default=TABLE)
     ap.add_argument("--target-ms", type=float, default=20.0)
     ap.add_argument("--verbose", action="store_true", help="log every shape timed")
-    ap.add_argument("--what", default="swept,classic", help="swept, classic or both")
+    ap.add_argument("--what", default="swept,classic", help="comma list of swept, classic, batch")
     args = ap.parse_args()
     names = {"heat": 0, "ks": 1, "euler": 2}
     schemes = [names[s] for s in args.schemes.split(",")]
@@ -196,6 +263,8 @@ def main():
              verbose=args.verbose)
     if "classic" in what:
         tune_classic(schemes, range(a, b + 1), target_s=args.target_ms / 1000.0, table=args.table, log=log)
+    if "batch" in what:
+        tune_batch(schemes, range(max(a, 8), min(b, 18) + 1), table=args.table, log=log)
 
 
 if __name__ == "__main__":

@@ -12,6 +12,7 @@
 #include <string>
 
 #include "../../paper_1705_03162_amd/csrc/batch.hip"
+#include "../../paper_1705_03162_amd/csrc/tune.cpp"
 #include "tile_emu.hpp"
 
 namespace sw {
@@ -105,9 +106,6 @@ hipError_t launch_stamp(uint64_t *stamps, int idx, hipStream_t st)
 
 int batch_blocks_per_cu(int, int) { return 2; }
 int persistent_blocks_per_cu(int, int) { return 2; }
-
-// No tuning table in this build: batched tiles take the most points per lane.
-bool tuned_batch_points(const sw_problem &, int *) { return false; }
 
 hipError_t launch_zero_words(void *p, int64_t count, hipStream_t st)
 {

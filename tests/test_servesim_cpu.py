@@ -10,6 +10,7 @@ first served, cancellation) must hold.
 import ctypes
 import os
 import subprocess
+import sys
 import time
 
 import numpy as np
@@ -316,3 +317,38 @@ def test_async_submit_waits_for_the_submitting_stream(sim, oracle_mod, serve):
         sim.servesim_stream_destroy(stream)
         same = [np.array_equal(x, oracle_mod.solve(p, ic)) for (p, ic), x in zip(probs, snaps)]
         assert all(same) if use_async else not any(same)
+
+
+def test_batch_shape_from_the_tuning_table(tmp_path):
+    """Batched tiles take the points per lane of the table's "batch" row for the size
+    class (the most that divide n/64 up to it), else the most up to 8."""
+    table = tmp_path / "tune.txt"
+    table.write_text("batch 0 12 2\nbatch 1 12 4\nbatch 0 14 8\n")
+    code = f"""
+import ctypes, os, sys
+sys.path.insert(0, {ROOT!r})
+os.environ["SWEPT_TUNE_FILE"] = {str(table)!r}
+import numpy as np
+import workloads as W
+from paper_1705_03162_amd import _native as N
+L = ctypes.CDLL({LIB!r})
+for name in ("batch_create", "batch_submit", "batch_ticket_info", "batch_destroy"):
+    fn = getattr(L, name); fn.restype, fn.argtypes = N.SIGNATURES[name]
+cfg = N.SwBatchConfig(1 << 30, 0, 0, 0, 0)
+h = ctypes.c_void_p(); assert L.batch_create(ctypes.byref(cfg), ctypes.byref(h)) == 0
+x = np.zeros(1 << 16)
+out = []
+for prob in (W.heat_problem(4096, 10), W.ks_problem(4096, 10), W.heat_problem(1 << 14, 10),
+             W.heat_problem(8192, 10), W.ks_problem(3 * 64, 10), W.sod_problem(4096, 10)):
+    p = N.problem_struct(prob); t = ctypes.c_uint64()
+    assert L.batch_submit(h, ctypes.byref(p), x.ctypes.data, ctypes.byref(t)) == 0
+    i = N.SwTicketInfo(); assert L.batch_ticket_info(h, t, ctypes.byref(i)) == 0
+    out.append(i.width)
+L.batch_destroy(h)
+print(out)
+"""
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stderr
+    # heat 2^12 -> table 2; KS 2^12 -> 4; heat 2^14 -> 8; heat 2^13 -> nearest smaller class (12): 2;
+    # KS n = 192 (n/64 = 3) -> 1 (the table's cap, but only 1 divides); Sod: no row -> most up to 8
+    assert r.stdout.strip() == str([128, 256, 512, 128, 64, 512])
