@@ -133,6 +133,8 @@ def _table(kind="swept"):
             if parts[0] == "classic":
                 if kind == "classic":
                     out[(int(parts[1]), int(parts[2]))] = int(parts[3])
+            elif parts[0] == "batch":
+                continue
             elif kind == "swept":
                 s, lg, w, t = (int(x) for x in parts[:4])
                 out[(s, lg)] = (w, t)
