@@ -110,8 +110,13 @@ __device__ __forceinline__ void level_exchange(double (&dst)[Sch::NV][P], const 
 // however many points a lane holds.  A wave with no point inside skips the level
 // (after publishing its boundary values for its neighbours), which recovers most
 // of the idle half of a triangle in multi-wave tiles.
+//
+// qa, qb: the wave-uniform lane quotients of the set's ends relative to the first point
+// the lanes hold, lo = P qa + ra and hi = P qb + rb with the compile-time residues ra,
+// rb; run_group derives them from one pair per group of levels, so a level spends no
+// scalar arithmetic on them and its lane compares repeat within the group.
 template <class Sch, int P, bool ODD, bool MULTI, bool WALL, bool INC, int SMOD>
-__device__ __forceinline__ void level_step(const TileArgs &a, int g, int NW, int s, int m, int org,
+__device__ __forceinline__ void level_step(const TileArgs &a, int g, int NW, int s, int org, int qa, int qb,
                                            const double (&src)[Sch::NV][P], double (&dst)[Sch::NV][P],
                                            const double (&hl)[Sch::NV][Sch::R],
                                            const double (&hr)[Sch::NV][Sch::R],
@@ -138,17 +143,14 @@ __device__ __forceinline__ void level_step(const TileArgs &a, int g, int NW, int
         __syncthreads();
     }
     const int half = a.w >> 1;
-    // the computed set relative to the first point the lanes hold (org: 0 for the whole
-    // tile, w/2 - 32 P for a one-wave layout packed around the tile centre)
-    const int lo = __builtin_amdgcn_readfirstlane(half - R * m - org);
-    const int hi = __builtin_amdgcn_readfirstlane(half + R * m - org);
+    constexpr int RA = pos_mod(INC ? -R * SMOD : R * SMOD, P);   // lo mod P
+    constexpr int RB = pos_mod(INC ? R * SMOD : -R * SMOD, P);   // hi mod P
     // first lane of this wave (a one-wave tile is lane 0 onwards)
     const int base = MULTI ? __builtin_amdgcn_readfirstlane(g & ~63) : 0;
     if (MULTI) {
         // lanes of this wave holding at least one computed point: [lmin, lmax); a
         // one-wave tile always holds some (the computed set is never empty)
-        int lmin, lmax;
-        element_lane_span(P, R, INC, SMOD, lo, hi, base, lmin, lmax);
+        const int lmin = qa - base, lmax = qb - base + (RB > 0 ? 1 : 0);
         if (!(lmin < 64 && lmax > 0 && lmin < lmax)) return;
     }
 
@@ -245,9 +247,8 @@ __device__ __forceinline__ void level_step(const TileArgs &a, int g, int NW, int
     bool in[P];
 #pragma unroll
     for (int k = 0; k < P; ++k) {
-        // la, lb take two values each over k: four distinct lane compares per level
-        int la, lb;
-        element_lane_bounds(P, R, INC, SMOD, lo, hi, base, k, la, lb);
+        // element k is computed on lanes [la, lb); la, lb take two values each over k
+        const int la = (k >= RA ? qa : qa + 1) - base, lb = (k < RB ? qb + 1 : qb) - base;
         in[k] = lane >= la && lane < lb;
     }
     if constexpr (Sch::LANE_EXCHANGE && !MULTI && !WALL) {
@@ -259,11 +260,15 @@ __device__ __forceinline__ void level_step(const TileArgs &a, int g, int NW, int
     Sch::template level<P, MULTI || Sch::SELECT_ONE_WAVE>(dst, ext, ODD, a.c, in);
 }
 
+constexpr int ilog2(int x) { return x <= 1 ? 0 : 1 + ilog2(x / 2); }
+
 // Levels s0 + U, s0 + U + 1, ... of one aligned group (s0 = A mod G, so the
 // row parity and the residues of the computed set are compile-time).  m = s for
-// a widening segment, m = mtop - s for a narrowing one.
+// a widening segment, m = mtop - s for a narrowing one.  The set's ends move by r
+// per level, so their lane quotients at level s0 + U are the group's (qa0, qb0)
+// plus compile-time offsets.
 template <class Sch, int P, bool MULTI, bool WALL, bool INC, int A, int U, int G>
-__device__ __forceinline__ void run_group(const TileArgs &a, int g, int NW, int s0, int s_last, int mtop,
+__device__ __forceinline__ void run_group(const TileArgs &a, int g, int NW, int s0, int s_last, int qa0, int qb0,
                                           int org, bool full, double (&r0)[Sch::NV][P], double (&r1)[Sch::NV][P],
                                           const double (&hl)[Sch::NV][Sch::R],
                                           const double (&hr)[Sch::NV][Sch::R],
@@ -272,14 +277,20 @@ __device__ __forceinline__ void run_group(const TileArgs &a, int g, int NW, int 
     if constexpr (U < G) {
         const int s = s0 + U;
         if (full || s <= s_last) {
-            const int m = INC ? s : mtop - s;
-            constexpr int SMOD = (A + U) % G;
+            constexpr int R = Sch::R, SMOD = (A + U) % G, S0 = A % G;
+            constexpr int RA0 = pos_mod(INC ? -R * S0 : R * S0, P), RB0 = pos_mod(INC ? R * S0 : -R * S0, P);
+            constexpr int RA = pos_mod(INC ? -R * SMOD : R * SMOD, P), RB = pos_mod(INC ? R * SMOD : -R * SMOD, P);
+            constexpr int D = INC ? -R * U : R * U;   // lo has moved by D since s0, hi by -D
+            static_assert((RA0 + D - RA) % P == 0 && (RB0 - D - RB) % P == 0, "ends stay on their residues");
+            constexpr int DA = (RA0 + D - RA) / P, DB = (RB0 - D - RB) / P;
             if constexpr (((A + U) & 1) != 0)
-                level_step<Sch, P, true, MULTI, WALL, INC, SMOD>(a, g, NW, s, m, org, r0, r1, hl, hr, xch);
+                level_step<Sch, P, true, MULTI, WALL, INC, SMOD>(a, g, NW, s, org, qa0 + DA, qb0 + DB, r0, r1, hl,
+                                                                 hr, xch);
             else
-                level_step<Sch, P, false, MULTI, WALL, INC, SMOD>(a, g, NW, s, m, org, r1, r0, hl, hr, xch);
-            run_group<Sch, P, MULTI, WALL, INC, A, U + 1, G>(a, g, NW, s0, s_last, mtop, org, full, r0, r1, hl,
-                                                             hr, xch);
+                level_step<Sch, P, false, MULTI, WALL, INC, SMOD>(a, g, NW, s, org, qa0 + DA, qb0 + DB, r1, r0, hl,
+                                                                  hr, xch);
+            run_group<Sch, P, MULTI, WALL, INC, A, U + 1, G>(a, g, NW, s0, s_last, qa0, qb0, org, full, r0, r1,
+                                                             hl, hr, xch);
         }
     }
 }
@@ -292,12 +303,28 @@ __device__ __forceinline__ void run_segment(const TileArgs &a, int g, int NW, in
                                             const double (&hr)[Sch::NV][Sch::R],
                                             double (*xch)[16][2][Sch::NV][Sch::R], int org = 0)
 {
-    constexpr int G = group_len(P, Sch::R);
-    int s0 = s_first;
-    for (; s0 + G - 1 <= s_last; s0 += G)
-        run_group<Sch, P, MULTI, WALL, INC, A, 0, G>(a, g, NW, s0, s_last, mtop, org, true, r0, r1, hl, hr, xch);
-    if (s0 <= s_last)
-        run_group<Sch, P, MULTI, WALL, INC, A, 0, G>(a, g, NW, s0, s_last, mtop, org, false, r0, r1, hl, hr, xch);
+    constexpr int R = Sch::R, G = group_len(P, R), S0 = A % G;
+    constexpr int RA0 = pos_mod(INC ? -R * S0 : R * S0, P), RB0 = pos_mod(INC ? R * S0 : -R * S0, P);
+    const int half = a.w >> 1;
+    // the computed set [lo, hi) relative to the first point the lanes hold (org: 0 for
+    // the whole tile, w/2 - 32 P for a one-wave layout packed around the tile centre)
+    // lies inside the lanes' points, so lo - ra and hi - rb are non-negative multiples of P
+    auto quotients = [&](int s0, int &qa0, int &qb0) {
+        const int m0 = INC ? s0 : mtop - s0;
+        qa0 = __builtin_amdgcn_readfirstlane((half - R * m0 - org - RA0) >> ilog2(P));
+        qb0 = __builtin_amdgcn_readfirstlane((half + R * m0 - org - RB0) >> ilog2(P));
+    };
+    int s0 = s_first, qa0, qb0;
+    for (; s0 + G - 1 <= s_last; s0 += G) {
+        quotients(s0, qa0, qb0);
+        run_group<Sch, P, MULTI, WALL, INC, A, 0, G>(a, g, NW, s0, s_last, qa0, qb0, org, true, r0, r1, hl, hr,
+                                                     xch);
+    }
+    if (s0 <= s_last) {
+        quotients(s0, qa0, qb0);
+        run_group<Sch, P, MULTI, WALL, INC, A, 0, G>(a, g, NW, s0, s_last, qa0, qb0, org, false, r0, r1, hl, hr,
+                                                     xch);
+    }
 }
 
 template <class Sch, int P, bool MULTI, bool WALL>
