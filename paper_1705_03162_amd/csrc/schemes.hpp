@@ -11,6 +11,10 @@
 // so the P independent updates form one block the compiler can interleave (hides
 // FP64 latency when few waves are resident); without it each point is a branch
 // (exec-masked regions), which the host evaluation of single points uses.
+// FREE_ONE_WAVE: one-wave tiles may update every point of a narrowing level (in[] all
+// set) and store the few finished boundary points to LDS instead of selecting
+// (swept_tile.hpp, free_class and level_step); on for heat, whose three-instruction
+// update makes the selects its largest overhead.
 //
 //   Heat  (Appendix B, Eq. Heatdisc):  T' = Fo (T_{i+1} + T_{i-1}) + (1 - 2 Fo) T_i,
 //         the Fo product fused with the addition
@@ -56,6 +60,7 @@ SW_HD double sw_fabs(double x) { return fabs(x); }
 struct Heat {
     static constexpr int R = 1, S = 1, NV = 1;
     static constexpr bool SELECT_ONE_WAVE = true;
+    static constexpr bool FREE_ONE_WAVE = true;
     static constexpr bool LANE_EXCHANGE = false;    // no per-cell quantity shared by neighbours
     template <int P, bool SEL = true>
     SW_HD static void level(double (&dst)[NV][P], const double (&ext)[NV][P + 2 * R],
@@ -80,6 +85,7 @@ struct Heat {
 struct KS {
     static constexpr int R = 2, S = 2, NV = 1;
     static constexpr bool SELECT_ONE_WAVE = true;
+    static constexpr bool FREE_ONE_WAVE = false;   // measured slower (LDS stores of fresh results)
     static constexpr bool LANE_EXCHANGE = false;
     // g_i(v) = -f_i(v) = (v_{i+1}^2 - v_{i-1}^2)/(4dx) + (v_{i+1} + v_{i-1} - 2v_i)/dx^2
     //                   + (v_{i+2} + v_{i-2} - 4(v_{i+1} + v_{i-1}) + 6v_i)/dx^4,
@@ -116,6 +122,7 @@ struct KS {
 struct Euler {
     static constexpr int R = 2, S = 2, NV = 3;
     static constexpr bool SELECT_ONE_WAVE = true;
+    static constexpr bool FREE_ONE_WAVE = false;   // not measured in a select-free class
     // Pressures, pressure ratios and interface fluxes belong to cells and interfaces, so
     // a lane may take its neighbours' values instead of evaluating them on its halo.
     static constexpr bool LANE_EXCHANGE = true;

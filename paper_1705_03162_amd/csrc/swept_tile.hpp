@@ -18,6 +18,9 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+#include <utility>
+
 #include "kernels.hpp"
 
 namespace sw {
@@ -103,6 +106,53 @@ __device__ __forceinline__ void level_exchange(double (&dst)[Sch::NV][P], const 
     }
 }
 
+// Select-free narrowing (see level_step) in class P of a one-wave tile, for schemes that
+// enable it, where it issues fewer instructions per level than selecting the computed
+// set: 4r boundary points, each a scalar lane mask, an address select and NV LDS stores,
+// against two selects per point and variable (heat: P >= 8).
+template <class Sch, int P>
+constexpr bool free_class()
+{
+    return Sch::FREE_ONE_WAVE && 4 * Sch::R * (2 + Sch::NV) < 2 * P * Sch::NV;
+}
+
+// LDS rows of a one-wave tile: tile point x at x + x/16 (one padding double per 16,
+// which keeps the stride-P accesses of every class layout and the point-major passes
+// free of bank conflicts).  Tiles of 8 or more points per lane also hold a sink in each
+// row for stores that no lane needs: one double per lane, the padding double after
+// 16-point block l for lane l when the row has 64 blocks (w = 1024), else 64 doubles
+// appended to the row.
+constexpr int wave_span(int P0) { return 68 * P0 + (P0 == 8 ? 64 : 0); }
+__device__ __forceinline__ int lds_pos(int x) { return x + (x >> 4); }
+template <int P0>
+__device__ __forceinline__ int lds_sink(int lane)
+{
+    static_assert(P0 == 8 || P0 == 16, "the LDS rows hold a sink at 8 and 16 points per lane");
+    if constexpr (P0 == 16) return 17 * lane + 16;
+    else return 68 * P0 + lane;
+}
+
+constexpr int floor_div(int x, int m) { return x >= 0 ? x / m : -((-x + m - 1) / m); }
+
+// f(std::integral_constant<int, i>) for i = 0 .. N-1, the index a compile-time constant.
+template <class F, int... I>
+__device__ __forceinline__ void unroll_seq(F &&f, std::integer_sequence<int, I...>)
+{
+    (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, class F>
+__device__ __forceinline__ void unroll(F &&f)
+{
+    unroll_seq(f, std::make_integer_sequence<int, N>{});
+}
+
+// Lane l (wave-uniform, 0 <= l < 64) as a per-lane condition: one scalar shift builds the
+// mask, and selects take it as their condition operand (no vector compare).
+__device__ __forceinline__ bool is_lane(int l)
+{
+    return __builtin_amdgcn_inverse_ballot_w64(1ull << l);
+}
+
 // One level of a tile: gather the source row with halos, then update the points
 // of the computed set [w/2 - r m, w/2 + r m).  Element k of the wave's lanes is
 // inside for a contiguous range of lanes whose ends take only two values each
@@ -115,13 +165,23 @@ __device__ __forceinline__ void level_exchange(double (&dst)[Sch::NV][P], const 
 // the lanes hold, lo = P qa + ra and hi = P qb + rb with the compile-time residues ra,
 // rb; run_group derives them from one pair per group of levels, so a level spends no
 // scalar arithmetic on them and its lane compares repeat within the group.
-template <class Sch, int P, bool ODD, bool MULTI, bool WALL, bool INC, int SMOD>
+//
+// Narrowing levels of a one-wave class layout where free_class holds (P0 > 0: the tile's
+// points per lane; `stage` its LDS rows) update every point of the layout unconditionally:
+// nothing outside the computed set is read again, but a level's boundary points
+// [lo, lo + 2r) and [hi - 2r, hi) are final in its row (the next level of the same
+// parity is narrower by 2r per side), so the level after it stores them from its source
+// row to the LDS rows, before the level after that overwrites them; the other lanes
+// store to their sink, so the store needs no branch.  The last level's points are
+// parked with its row, and a Diamond's first narrowing level stores the widest level's.
+template <class Sch, int P, bool ODD, bool MULTI, bool WALL, bool INC, int SMOD, int P0 = 0>
 __device__ __forceinline__ void level_step(const TileArgs &a, int g, int NW, int s, int org, int qa, int qb,
                                            const double (&src)[Sch::NV][P], double (&dst)[Sch::NV][P],
                                            const double (&hl)[Sch::NV][Sch::R],
                                            const double (&hr)[Sch::NV][Sch::R],
-                                           double (*xch)[16][2][Sch::NV][Sch::R])
+                                           double (*xch)[16][2][Sch::NV][Sch::R], double *stage = nullptr)
 {
+    constexpr bool FREE = !MULTI && P0 > 0 && !INC && free_class<Sch, P>();
     constexpr int NV = Sch::NV, R = Sch::R;
     const int lane = g & 63, wave = g >> 6, buf = s & 1;
     if (MULTI) {
@@ -244,20 +304,43 @@ __device__ __forceinline__ void level_step(const TileArgs &a, int g, int NW, int
                     if (x0 + P + i >= half) ext[v][R + P + i] = a.c.ghost_r[v];
         }
     }
+    if constexpr (FREE) {
+        // the previous level's boundary points, [lo', lo' + 2r) and [hi' - 2r, hi') with
+        // lo' = lo - r and hi' = hi + r, are final in the source row: into its LDS row
+        // before the level after this one overwrites them (the values are long computed,
+        // so the stores do not wait on this level's arithmetic)
+        constexpr int SPAN = wave_span(P0);
+        double *own = stage + (ODD ? 0 : SPAN) + lds_pos(x0);
+        double *sink = stage + (ODD ? 0 : SPAN) + lds_sink<P0>(lane);
+        unroll<2 * R>([&](auto I) {
+            constexpr int xl = RA - R + decltype(I)::value, xr = RB - R + decltype(I)::value;
+            constexpr int kl = pos_mod(xl, P), kr = pos_mod(xr, P);
+            double *pl = is_lane(qa + floor_div(xl, P)) ? own + kl : sink;
+            double *pr = is_lane(qb + floor_div(xr, P)) ? own + kr : sink;
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                pl[2 * v * SPAN] = src[v][kl];
+                pr[2 * v * SPAN] = src[v][kr];
+            }
+        });
+    }
     bool in[P];
 #pragma unroll
     for (int k = 0; k < P; ++k) {
         // element k is computed on lanes [la, lb); la, lb take two values each over k
         const int la = (k >= RA ? qa : qa + 1) - base, lb = (k < RB ? qb + 1 : qb) - base;
-        in[k] = lane >= la && lane < lb;
+        in[k] = FREE || (lane >= la && lane < lb);
     }
+    constexpr bool SEL = !FREE && (MULTI || Sch::SELECT_ONE_WAVE);
+    const bool widest = s == a.H && a.kind != PH_UP;
     if constexpr (Sch::LANE_EXCHANGE && !MULTI && !WALL) {
-        if (__builtin_expect(!(s == a.H && a.kind != PH_UP), 1)) {  // the widest level reads the patched halo
-            level_exchange<Sch, P, Sch::SELECT_ONE_WAVE>(dst, ext, ODD, a.c, in);
-            return;
-        }
+        if (__builtin_expect(!widest, 1))   // the widest level reads the patched halo
+            level_exchange<Sch, P, SEL>(dst, ext, ODD, a.c, in);
+        else
+            Sch::template level<P, SEL>(dst, ext, ODD, a.c, in);
+    } else {
+        Sch::template level<P, SEL>(dst, ext, ODD, a.c, in);
     }
-    Sch::template level<P, MULTI || Sch::SELECT_ONE_WAVE>(dst, ext, ODD, a.c, in);
 }
 
 constexpr int ilog2(int x) { return x <= 1 ? 0 : 1 + ilog2(x / 2); }
@@ -267,12 +350,12 @@ constexpr int ilog2(int x) { return x <= 1 ? 0 : 1 + ilog2(x / 2); }
 // a widening segment, m = mtop - s for a narrowing one.  The set's ends move by r
 // per level, so their lane quotients at level s0 + U are the group's (qa0, qb0)
 // plus compile-time offsets.
-template <class Sch, int P, bool MULTI, bool WALL, bool INC, int A, int U, int G>
+template <class Sch, int P, bool MULTI, bool WALL, bool INC, int A, int U, int G, int P0>
 __device__ __forceinline__ void run_group(const TileArgs &a, int g, int NW, int s0, int s_last, int qa0, int qb0,
                                           int org, bool full, double (&r0)[Sch::NV][P], double (&r1)[Sch::NV][P],
                                           const double (&hl)[Sch::NV][Sch::R],
                                           const double (&hr)[Sch::NV][Sch::R],
-                                          double (*xch)[16][2][Sch::NV][Sch::R])
+                                          double (*xch)[16][2][Sch::NV][Sch::R], double *stage)
 {
     if constexpr (U < G) {
         const int s = s0 + U;
@@ -284,24 +367,26 @@ __device__ __forceinline__ void run_group(const TileArgs &a, int g, int NW, int 
             static_assert((RA0 + D - RA) % P == 0 && (RB0 - D - RB) % P == 0, "ends stay on their residues");
             constexpr int DA = (RA0 + D - RA) / P, DB = (RB0 - D - RB) / P;
             if constexpr (((A + U) & 1) != 0)
-                level_step<Sch, P, true, MULTI, WALL, INC, SMOD>(a, g, NW, s, org, qa0 + DA, qb0 + DB, r0, r1, hl,
-                                                                 hr, xch);
+                level_step<Sch, P, true, MULTI, WALL, INC, SMOD, P0>(a, g, NW, s, org, qa0 + DA, qb0 + DB, r0, r1,
+                                                                     hl, hr, xch, stage);
             else
-                level_step<Sch, P, false, MULTI, WALL, INC, SMOD>(a, g, NW, s, org, qa0 + DA, qb0 + DB, r1, r0, hl,
-                                                                  hr, xch);
-            run_group<Sch, P, MULTI, WALL, INC, A, U + 1, G>(a, g, NW, s0, s_last, qa0, qb0, org, full, r0, r1,
-                                                             hl, hr, xch);
+                level_step<Sch, P, false, MULTI, WALL, INC, SMOD, P0>(a, g, NW, s, org, qa0 + DA, qb0 + DB, r1, r0,
+                                                                      hl, hr, xch, stage);
+            run_group<Sch, P, MULTI, WALL, INC, A, U + 1, G, P0>(a, g, NW, s0, s_last, qa0, qb0, org, full, r0,
+                                                                 r1, hl, hr, xch, stage);
         }
     }
 }
 
 // Levels [s_first, s_last] (s_first = A mod G) in full groups plus one partial group.
-template <class Sch, int P, bool MULTI, bool WALL, bool INC, int A = 1>
+// P0 > 0: a one-wave class layout of a tile with P0 points per lane, LDS rows `stage`.
+template <class Sch, int P, bool MULTI, bool WALL, bool INC, int A = 1, int P0 = 0>
 __device__ __forceinline__ void run_segment(const TileArgs &a, int g, int NW, int s_first, int s_last,
                                             int mtop, double (&r0)[Sch::NV][P], double (&r1)[Sch::NV][P],
                                             const double (&hl)[Sch::NV][Sch::R],
                                             const double (&hr)[Sch::NV][Sch::R],
-                                            double (*xch)[16][2][Sch::NV][Sch::R], int org = 0)
+                                            double (*xch)[16][2][Sch::NV][Sch::R], int org = 0,
+                                            double *stage = nullptr)
 {
     constexpr int R = Sch::R, G = group_len(P, R), S0 = A % G;
     constexpr int RA0 = pos_mod(INC ? -R * S0 : R * S0, P), RB0 = pos_mod(INC ? R * S0 : -R * S0, P);
@@ -317,13 +402,13 @@ __device__ __forceinline__ void run_segment(const TileArgs &a, int g, int NW, in
     int s0 = s_first, qa0, qb0;
     for (; s0 + G - 1 <= s_last; s0 += G) {
         quotients(s0, qa0, qb0);
-        run_group<Sch, P, MULTI, WALL, INC, A, 0, G>(a, g, NW, s0, s_last, qa0, qb0, org, true, r0, r1, hl, hr,
-                                                     xch);
+        run_group<Sch, P, MULTI, WALL, INC, A, 0, G, P0>(a, g, NW, s0, s_last, qa0, qb0, org, true, r0, r1, hl,
+                                                         hr, xch, stage);
     }
     if (s0 <= s_last) {
         quotients(s0, qa0, qb0);
-        run_group<Sch, P, MULTI, WALL, INC, A, 0, G>(a, g, NW, s0, s_last, qa0, qb0, org, false, r0, r1, hl, hr,
-                                                     xch);
+        run_group<Sch, P, MULTI, WALL, INC, A, 0, G, P0>(a, g, NW, s0, s_last, qa0, qb0, org, false, r0, r1, hl,
+                                                         hr, xch, stage);
     }
 }
 
@@ -363,8 +448,6 @@ __device__ __forceinline__ void run_levels(const TileArgs &a, int g, int NW, dou
 // LDS position of tile point x: x + x/16 (one padding double per 16), which keeps
 // the stride-P accesses of every class layout and the point-major passes free of
 // bank conflicts.
-constexpr int wave_span(int P0) { return 68 * P0; }   // w + w/16 doubles per row, w = 64 P0
-__device__ __forceinline__ int lds_pos(int x) { return x + (x >> 4); }
 constexpr int min_class(int P0) { return P0 < 2 ? P0 : 2; }
 
 template <class Sch, int P, int SPAN>
@@ -381,18 +464,38 @@ __device__ __forceinline__ void fetch_rows(const double *stage, int org, int lan
         }
 }
 
-template <class Sch, int P, int SPAN>
-__device__ __forceinline__ void park_rows(double *stage, int org, int lane, const double (&r0)[Sch::NV][P],
-                                          const double (&r1)[Sch::NV][P])
+// Park the rows in LDS at the end of a class.  After select levels the registers mirror
+// LDS outside the computed sets and the whole layout is written back; after select-free
+// levels only the rows' computed sets are valid: row q of the last level s on the set
+// of level s, the other row on the set of level s - 1 (everything else in LDS is already
+// current, and a widening run leaves nothing else behind either).
+template <class Sch, int P, int P0>
+__device__ __forceinline__ void park_rows(const TileArgs &a, double *stage, int org, int lane, int s_last,
+                                          const double (&r0)[Sch::NV][P], const double (&r1)[Sch::NV][P])
 {
+    constexpr int R = Sch::R, SPAN = wave_span(P0);
+    const int half = a.w >> 1;
+    const int mq = half_width(a, s_last), mp = half_width(a, s_last - 1);
+    // relative to the layout: [lo, hi) of the last level's row and of the other row
+    const int lo_q = half - R * mq - org, hi_q = half + R * mq - org;
+    const int lo_p = half - R * mp - org, hi_p = half + R * mp - org;
+    const bool q1 = (s_last & 1) != 0;   // the last level wrote row 1
 #pragma unroll
-    for (int v = 0; v < Sch::NV; ++v)
-#pragma unroll
-        for (int k = 0; k < P; ++k) {
-            const int i = lds_pos(org + lane * P + k);
-            stage[(2 * v + 0) * SPAN + i] = r0[v][k];
-            stage[(2 * v + 1) * SPAN + i] = r1[v][k];
+    for (int k = 0; k < P; ++k) {
+        const int x = lane * P + k;
+        const int i = lds_pos(org + x);
+        bool in0 = true, in1 = true;
+        if constexpr (free_class<Sch, P>()) {
+            const bool in_q = x >= lo_q && x < hi_q, in_p = x >= lo_p && x < hi_p;
+            in0 = q1 ? in_p : in_q;
+            in1 = q1 ? in_q : in_p;
         }
+#pragma unroll
+        for (int v = 0; v < Sch::NV; ++v) {
+            if (in0) stage[(2 * v + 0) * SPAN + i] = r0[v][k];
+            if (in1) stage[(2 * v + 1) * SPAN + i] = r1[v][k];
+        }
+    }
     __syncthreads();
 }
 
@@ -411,8 +514,9 @@ __device__ __forceinline__ void wave_narrow(const TileArgs &a, int lane, double 
         const int org = (a.w >> 1) - 32 * P;
         double r0[NV][P], r1[NV][P];
         fetch_rows<Sch, P, SPAN>(stage, org, lane, r0, r1);
-        run_segment<Sch, P, false, WALL, false, 1>(a, lane, 1, s, cap, mtop, r0, r1, hl, hr, nullptr, org);
-        park_rows<Sch, P, SPAN>(stage, org, lane, r0, r1);
+        run_segment<Sch, P, false, WALL, false, 1, P0>(a, lane, 1, s, cap, mtop, r0, r1, hl, hr, nullptr, org,
+                                                       stage);
+        park_rows<Sch, P, P0>(a, stage, org, lane, cap, r0, r1);
     }
     if constexpr (P > min_class(P0)) {
         if (s_last >= s_next)
@@ -438,20 +542,22 @@ __device__ __forceinline__ void wave_widen(const TileArgs &a, int lane, double *
         if (s <= cap) {
             double r0[NV][P], r1[NV][P];
             fetch_rows<Sch, P, SPAN>(stage, org, lane, r0, r1);
-            run_segment<Sch, P, false, WALL, true, A>(a, lane, 1, s, cap, 0, r0, r1, hl, hr, nullptr, org);
-            park_rows<Sch, P, SPAN>(stage, org, lane, r0, r1);
+            run_segment<Sch, P, false, WALL, true, A, P0>(a, lane, 1, s, cap, 0, r0, r1, hl, hr, nullptr, org,
+                                                          stage);
+            park_rows<Sch, P, P0>(a, stage, org, lane, cap, r0, r1);
         }
         if (cap < top) wave_widen<Sch, 2 * P, P0, WALL>(a, lane, stage, cap + 1, top, n_last, hl, hr);
     } else {
         double r0[NV][P], r1[NV][P];
         fetch_rows<Sch, P, SPAN>(stage, org, lane, r0, r1);
-        run_segment<Sch, P, false, WALL, true, A>(a, lane, 1, s, top, 0, r0, r1, hl, hr, nullptr, org);
+        run_segment<Sch, P, false, WALL, true, A, P0>(a, lane, 1, s, top, 0, r0, r1, hl, hr, nullptr, org, stage);
         const int mtop = 2 * a.H;
         const int s_next = P > min_class(P0) ? mtop - 16 * P / R + 1 : n_last + 1;
         const int cap = n_last < s_next - 1 ? n_last : s_next - 1;
         if (top + 1 <= cap)
-            run_segment<Sch, P, false, WALL, false, 1>(a, lane, 1, top + 1, cap, mtop, r0, r1, hl, hr, nullptr, org);
-        park_rows<Sch, P, SPAN>(stage, org, lane, r0, r1);
+            run_segment<Sch, P, false, WALL, false, 1, P0>(a, lane, 1, top + 1, cap, mtop, r0, r1, hl, hr, nullptr,
+                                                           org, stage);
+        park_rows<Sch, P, P0>(a, stage, org, lane, top + 1 <= cap ? cap : top, r0, r1);
         if constexpr (P > min_class(P0)) {
             if (n_last >= s_next) wave_narrow<Sch, P / 2, P0, WALL>(a, lane, stage, s_next, n_last, mtop, hl, hr);
         }
