@@ -116,6 +116,14 @@ constexpr bool free_class()
     return Sch::FREE_ONE_WAVE && 4 * Sch::R * (2 + Sch::NV) < 2 * P * Sch::NV;
 }
 
+// Select-free widening in the select-free classes where it pays: 4r points restored per
+// level, each a lane compare, two selects and one LDS load per variable (heat: P = 16).
+template <class Sch, int P>
+constexpr bool free_widen_class()
+{
+    return free_class<Sch, P>() && 4 * Sch::R * (1 + 3 * Sch::NV) < 2 * P * Sch::NV;
+}
+
 // LDS rows of a one-wave tile: tile point x at x + x/16 (one padding double per 16,
 // which keeps the stride-P accesses of every class layout and the point-major passes
 // free of bank conflicts).  Tiles of 8 or more points per lane also hold a sink in each
@@ -185,6 +193,7 @@ __device__ __forceinline__ void level_step(const TileArgs &a, int g, int NW, int
                                            double (*xch)[16][2][Sch::NV][Sch::R], double *stage = nullptr)
 {
     constexpr bool FREE = !MULTI && P0 > 0 && !INC && free_class<Sch, P>();
+    constexpr bool FREE_W = !MULTI && P0 > 0 && INC && free_widen_class<Sch, P>();
     constexpr int NV = Sch::NV, R = Sch::R;
     const int lane = g & 63, wave = g >> 6, buf = s & 1;
     if (MULTI) {
@@ -210,6 +219,24 @@ __device__ __forceinline__ void level_step(const TileArgs &a, int g, int NW, int
     constexpr int RB = pos_mod(INC ? R * SMOD : -R * SMOD, P);   // hi mod P
     // first lane of this wave (a one-wave tile is lane 0 onwards)
     const int base = MULTI ? __builtin_amdgcn_readfirstlane(g & ~63) : 0;
+    // select-free widening: the next level's halo [lo - 2r, lo) and [hi, hi + 2r) of the row
+    // being written keeps its inserted values, read from the LDS row before the update
+    // (every lane reads its own element, inside the layout) and selected back after it
+    double keep[2][2 * R][NV];
+    if constexpr (FREE_W) {
+        constexpr int SPAN = wave_span(P0);
+        const double *own = stage + (ODD ? SPAN : 0) + lds_pos(org + g * P);
+        unroll<2 * R>([&](auto I) {
+            constexpr int kl = pos_mod(RA - 2 * R + decltype(I)::value, P);
+            constexpr int kr = pos_mod(RB + decltype(I)::value, P);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                keep[0][decltype(I)::value][v] = own[2 * v * SPAN + kl];
+                keep[1][decltype(I)::value][v] = own[2 * v * SPAN + kr];
+            }
+        });
+    }
+
     if (MULTI) {
         // lanes of this wave holding at least one computed point: [lmin, lmax); a
         // one-wave tile always holds some (the computed set is never empty)
@@ -333,9 +360,9 @@ __device__ __forceinline__ void level_step(const TileArgs &a, int g, int NW, int
     for (int k = 0; k < P; ++k) {
         // element k is computed on lanes [la, lb); la, lb take two values each over k
         const int la = (k >= RA ? qa : qa + 1) - base, lb = (k < RB ? qb + 1 : qb) - base;
-        in[k] = FREE || (lane >= la && lane < lb);
+        in[k] = FREE || FREE_W || (lane >= la && lane < lb);
     }
-    constexpr bool SEL = !FREE && (MULTI || Sch::SELECT_ONE_WAVE);
+    constexpr bool SEL = !FREE && !FREE_W && (MULTI || Sch::SELECT_ONE_WAVE);
     if constexpr (Sch::LANE_EXCHANGE && !MULTI && !WALL) {
         if (__builtin_expect(!widest, 1))   // the widest level reads the patched halo
             level_exchange<Sch, P, SEL>(dst, ext, ODD, a.c, in);
@@ -343,6 +370,20 @@ __device__ __forceinline__ void level_step(const TileArgs &a, int g, int NW, int
             Sch::template level<P, SEL>(dst, ext, ODD, a.c, in);
     } else {
         Sch::template level<P, SEL>(dst, ext, ODD, a.c, in);
+    }
+    if constexpr (FREE_W) {
+        // lanes outside [0, 64) hold none of these points (the class's last level: the
+        // next level fetches a wider layout from LDS)
+        unroll<2 * R>([&](auto I) {
+            constexpr int xl = RA - 2 * R + decltype(I)::value, xr = RB + decltype(I)::value;
+            constexpr int kl = pos_mod(xl, P), kr = pos_mod(xr, P);
+            const bool tl = lane == qa + floor_div(xl, P), tr = lane == qb + floor_div(xr, P);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                dst[v][kl] = tl ? keep[0][decltype(I)::value][v] : dst[v][kl];
+                dst[v][kr] = tr ? keep[1][decltype(I)::value][v] : dst[v][kr];
+            }
+        });
     }
 }
 
