@@ -78,6 +78,11 @@ SMALL = [  # (problem factory, width, threads)
     (lambda: (W.Problem(W.KS, 3072, 421, 2.0 ** -8, 0.5, bc=W.DIRICHLET, bc_left=(0.4, 0, 0),
                         bc_right=(-0.2, 0, 0)), W.fourier_ic(3072, 21)), 1024, 64),
     (lambda: (W.sod_problem(2048, 777), W.sod_ic(2048)), 512, 64),        # P = 8, three variables
+    # heat on one-wave tiles of 8 points per lane (select-free narrowing in the 8-point class),
+    # an odd tile count, remainders, Dirichlet and insulated walls
+    (lambda: (W.heat_problem(2560, 1111, bc=W.DIRICHLET, bc_left=-0.4, bc_right=0.9),
+              W.fourier_ic(2560, 22)), 512, 64),
+    (lambda: (W.heat_problem(1536, 700, bc=W.REFLECTIVE), W.fourier_ic(1536, 23)), 512, 64),
     # Sod on one-wave tiles of 1, 2 and 4 points per lane (lane exchange of pressures, ratios
     # and fluxes), an odd tile count and remainders
     (lambda: (W.sod_problem(1280, 641), W.sod_ic(1280)), 256, 64),
@@ -276,8 +281,11 @@ def test_repeat_runs_bitwise_identical():
             torch.cuda.synchronize()
 
 
-def test_tile_shape_invariance_bitwise():
-    prob, ic = W.cfg_sweep(W.KS, 14, nsteps=2000)
+@pytest.mark.parametrize("scheme", [W.KS, W.HEAT])
+def test_tile_shape_invariance_bitwise(scheme):
+    """Every tile shape gives the same bits: one-wave tiles of 2 to 16 points per lane (whose
+    classes select or update select-free) and multi-wave tiles."""
+    prob, ic = W.cfg_sweep(scheme, 14, nsteps=2000)
     shapes = [(128, 64), (256, 64), (512, 64), (1024, 64), (1024, 128), (2048, 128), (2048, 256),
               (4096, 512), (1024, 512), (8192, 512)]
     outs = [gpu_solve(prob, ic, "swept", w, t) for w, t in shapes]
