@@ -15,6 +15,10 @@
 // set) and store the few finished boundary points to LDS instead of selecting
 // (swept_tile.hpp, free_class and level_step); on for heat, whose three-instruction
 // update makes the selects its largest overhead.
+// CLASS12: one-wave tiles of 16 points per lane add a 12-point class layout between the
+// 8- and 16-point ones (swept_tile.hpp, next_class); on for KS, where it cuts the lane
+// slots of the widest levels (heat's select-free 16-point levels already cost about as
+// little as selecting 12-point ones, and a class change more).
 //
 //   Heat  (Appendix B, Eq. Heatdisc):  T' = Fo (T_{i+1} + T_{i-1}) + (1 - 2 Fo) T_i,
 //         the Fo product fused with the addition
@@ -61,6 +65,7 @@ struct Heat {
     static constexpr int R = 1, S = 1, NV = 1;
     static constexpr bool SELECT_ONE_WAVE = true;
     static constexpr bool FREE_ONE_WAVE = true;
+    static constexpr bool CLASS12 = false;          // measured slower: 110.7 vs 109.3 us at 2^20
     static constexpr bool LANE_EXCHANGE = false;    // no per-cell quantity shared by neighbours
     template <int P, bool SEL = true>
     SW_HD static void level(double (&dst)[NV][P], const double (&ext)[NV][P + 2 * R],
@@ -86,6 +91,7 @@ struct KS {
     static constexpr int R = 2, S = 2, NV = 1;
     static constexpr bool SELECT_ONE_WAVE = true;
     static constexpr bool FREE_ONE_WAVE = false;   // measured slower: 122.4 vs 121.6 us at 2^20, 895 vs 823 at 2^23
+    static constexpr bool CLASS12 = true;
     static constexpr bool LANE_EXCHANGE = false;
     // g_i(v) = -f_i(v) = (v_{i+1}^2 - v_{i-1}^2)/(4dx) + (v_{i+1} + v_{i-1} - 2v_i)/dx^2
     //                   + (v_{i+2} + v_{i-2} - 4(v_{i+1} + v_{i-1}) + 6v_i)/dx^4,
@@ -125,6 +131,7 @@ struct Euler {
     static constexpr bool FREE_ONE_WAVE = false;   // not measured in a select-free class
     // Pressures, pressure ratios and interface fluxes belong to cells and interfaces, so
     // a lane may take its neighbours' values instead of evaluating them on its halo.
+    static constexpr bool CLASS12 = false;   // its tuned tiles have at most 8 points per lane
     static constexpr bool LANE_EXCHANGE = true;
 
     // Eq. EulerP with E the total energy per volume: P = (gamma-1)(E - (m u)/2), u = m/rho.

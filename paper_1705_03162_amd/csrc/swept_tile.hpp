@@ -109,11 +109,12 @@ __device__ __forceinline__ void level_exchange(double (&dst)[Sch::NV][P], const 
 // Select-free narrowing (see level_step) in class P of a one-wave tile, for schemes that
 // enable it, where it issues fewer instructions per level than selecting the computed
 // set: 4r boundary points, each a scalar lane mask, an address select and NV LDS stores,
-// against two selects per point and variable (heat: P >= 8).
+// against two selects per point and variable (heat: P = 8 and 16; the lanes' points must
+// not straddle a 16-point LDS block, so P divides 16).
 template <class Sch, int P>
 constexpr bool free_class()
 {
-    return Sch::FREE_ONE_WAVE && 4 * Sch::R * (2 + Sch::NV) < 2 * P * Sch::NV;
+    return Sch::FREE_ONE_WAVE && 16 % P == 0 && 4 * Sch::R * (2 + Sch::NV) < 2 * P * Sch::NV;
 }
 
 // Select-free widening in the select-free classes where it pays: 4r points restored per
@@ -387,7 +388,6 @@ __device__ __forceinline__ void level_step(const TileArgs &a, int g, int NW, int
     }
 }
 
-constexpr int ilog2(int x) { return x <= 1 ? 0 : 1 + ilog2(x / 2); }
 
 // One-wave level loops that cannot reach the widest level compile its test out, and the
 // widest level runs on its own.  Not for the scheme whose levels exchange per-cell
@@ -396,9 +396,9 @@ constexpr int ilog2(int x) { return x <= 1 ? 0 : 1 + ilog2(x / 2); }
 template <class Sch>
 constexpr bool peel_widest() { return !Sch::LANE_EXCHANGE; }
 
-// Levels s0 + U, s0 + U + 1, ... of one aligned group (s0 = A mod G, so the
-// row parity and the residues of the computed set are compile-time).  m = s for
-// a widening segment, m = mtop - s for a narrowing one.  The set's ends move by r
+// Levels s0 + U, s0 + U + 1, ... of one aligned group (widening: m = s and s0 = A
+// mod G; narrowing: m = mtop - s and m = -A mod G at s0; so the row parity and the
+// residues of the computed set are compile-time).  The set's ends move by r
 // per level, so their lane quotients at level s0 + U are the group's (qa0, qb0)
 // plus compile-time offsets.
 template <class Sch, int P, bool MULTI, bool WALL, bool INC, int A, int U, int G, int P0, bool WIDE>
@@ -429,7 +429,8 @@ __device__ __forceinline__ void run_group(const TileArgs &a, int g, int NW, int 
     }
 }
 
-// Levels [s_first, s_last] (s_first = A mod G) in full groups plus one partial group.
+// Levels [s_first, s_last] (aligned to residue A as in run_group) in full groups plus
+// one partial group.
 // P0 > 0: a one-wave class layout of a tile with P0 points per lane, LDS rows `stage`.
 template <class Sch, int P, bool MULTI, bool WALL, bool INC, int A = 1, int P0 = 0, bool WIDE = true>
 __device__ __forceinline__ void run_segment(const TileArgs &a, int g, int NW, int s_first, int s_last,
@@ -447,8 +448,8 @@ __device__ __forceinline__ void run_segment(const TileArgs &a, int g, int NW, in
     // lies inside the lanes' points, so lo - ra and hi - rb are non-negative multiples of P
     auto quotients = [&](int s0, int &qa0, int &qb0) {
         const int m0 = INC ? s0 : mtop - s0;
-        qa0 = __builtin_amdgcn_readfirstlane((half - R * m0 - org - RA0) >> ilog2(P));
-        qb0 = __builtin_amdgcn_readfirstlane((half + R * m0 - org - RB0) >> ilog2(P));
+        qa0 = __builtin_amdgcn_readfirstlane((int)((unsigned)(half - R * m0 - org - RA0) / P));
+        qb0 = __builtin_amdgcn_readfirstlane((int)((unsigned)(half + R * m0 - org - RB0) / P));
     };
     int s0 = s_first, qa0, qb0;
     for (; s0 + G - 1 <= s_last; s0 += G) {
@@ -487,19 +488,53 @@ __device__ __forceinline__ void run_levels(const TileArgs &a, int g, int NW, dou
 // of the lanes idle on average (the idle threads of the paper's Results).  A
 // one-wave tile therefore keeps both rows of the whole tile in LDS and holds in
 // registers only a class layout: the 64 P points [w/2 - 32 P, w/2 + 32 P) centred
-// in the tile, lane g owning P consecutive ones, with P the smallest power of two
-// (at least 2) whose layout holds the level's computed set and its halo,
-// r m + r <= 32 P.  At a change of class the lanes park their rows in LDS and fetch
+// in the tile, lane g owning P consecutive ones, with P the smallest class (2, 4, 8,
+// and for 16-point tiles 12 and 16) whose layout holds the level's computed set and
+// its halo, r m + r <= 32 P.  At a change of class the lanes park their rows in LDS and fetch
 // the next layout; positions outside the layout keep their values there (inserted
 // edges not yet reached by a widening set, finished values left behind by a
-// narrowing one).  The computed set then covers about three quarters of the lane
-// slots instead of half.  Row loads and stores go through the same LDS copy,
+// narrowing one).  The computed set then covers about four fifths of the lane slots
+// instead of half.  Row loads and stores go through the same LDS copy,
 // point-major, so every global access instruction moves 64 consecutive doubles.
 //
 // LDS position of tile point x: x + x/16 (one padding double per 16), which keeps
 // the stride-P accesses of every class layout and the point-major passes free of
 // bank conflicts.
 constexpr int min_class(int P0) { return P0 < 2 ? P0 : 2; }
+// The classes above and below P.  Tiles of 16 points per lane of a scheme with CLASS12
+// have a 12-point class between 8 and 16: the levels with 256 < r m + r <= 384 then run
+// at three quarters of the widest class's lane slots.
+template <class Sch>
+constexpr int next_class(int P0, int P)
+{
+    return Sch::CLASS12 && P0 == 16 && P == 8 ? 12 : (P == 12 ? 16 : 2 * P);
+}
+template <class Sch>
+constexpr int prev_class(int P0, int P)
+{
+    return Sch::CLASS12 && P0 == 16 && P == 16 ? 12 : (P == 12 ? 8 : P / 2);
+}
+
+// Widening from class P: the next class up starts at level m = 32 P / r (the first one
+// class P cannot hold) or a few levels earlier, at a multiple of its group length, so
+// that its levels keep compile-time residues from residue 0.
+template <class Sch, int P0, int P>
+constexpr int widen_switch()
+{
+    constexpr int x = 32 * P / Sch::R, G = group_len(next_class<Sch>(P0, P), Sch::R);
+    return x - x % G;
+}
+
+// Narrowing from class P (m = mtop - s): the next class down holds the levels with
+// m <= 32 Pp / r - 1 and starts at the first of them, where m = -1 modulo its group
+// length.  Narrowing segments take their compile-time residues from m (the residue A = 1
+// means m = -A at the segment's first level), which holds whatever mtop is modulo the
+// group length; mtop is even, so the row parity follows m's as well.
+template <class Sch, int P0, int P>
+__device__ __forceinline__ int narrow_switch(int mtop)
+{
+    return mtop - 32 * prev_class<Sch>(P0, P) / Sch::R + 1;
+}
 
 template <class Sch, int P, int SPAN>
 __device__ __forceinline__ void fetch_rows(const double *stage, int org, int lane, double (&r0)[Sch::NV][P],
@@ -550,16 +585,16 @@ __device__ __forceinline__ void park_rows(const TileArgs &a, double *stage, int 
     __syncthreads();
 }
 
-// Narrowing levels [s, s_last] (m = mtop - s) from class P downwards.  Class P holds
-// them while m >= 16 P / r (the smaller class's limit plus one); every class starts at
-// a level = 1 modulo its group length (mtop and 16 P / r are multiples of it).
+// Narrowing levels [s, s_last] (m = mtop - s) from class P downwards, each class
+// handing over to the next one down at narrow_switch.
 template <class Sch, int P, int P0, bool WALL>
 __device__ __forceinline__ void wave_narrow(const TileArgs &a, int lane, double *stage, int s, int s_last,
                                             int mtop, const double (&hl)[Sch::NV][Sch::R],
                                             const double (&hr)[Sch::NV][Sch::R])
 {
     constexpr int NV = Sch::NV, R = Sch::R, SPAN = wave_span(P0);
-    const int s_next = P > min_class(P0) ? mtop - 16 * P / R + 1 : s_last + 1;   // first level of P/2
+    int s_next = s_last + 1;   // first level of the class below
+    if constexpr (P > min_class(P0)) s_next = narrow_switch<Sch, P0, P>(mtop);
     const int cap = s_last < s_next - 1 ? s_last : s_next - 1;
     if (s <= cap) {
         const int org = (a.w >> 1) - 32 * P;
@@ -571,12 +606,13 @@ __device__ __forceinline__ void wave_narrow(const TileArgs &a, int lane, double 
     }
     if constexpr (P > min_class(P0)) {
         if (s_last >= s_next)
-            wave_narrow<Sch, P / 2, P0, WALL>(a, lane, stage, s > s_next ? s : s_next, s_last, mtop, hl, hr);
+            wave_narrow<Sch, prev_class<Sch>(P0, P), P0, WALL>(a, lane, stage, s > s_next ? s : s_next, s_last, mtop,
+                                                          hl, hr);
     }
 }
 
 // Widening levels [s, top] (m = s) from class P upwards; class P holds them while
-// r m + r <= 32 P, and the next class starts at m = 32 P / r (= 0 modulo its group
+// r m + r <= 32 P, and the next class starts at widen_switch (0 modulo its group
 // length; the smallest class starts at level 1).  The full-width class P0 also runs
 // a Diamond's narrowing levels [top + 1, n_last] before handing over to the classes
 // below it.
@@ -589,7 +625,8 @@ __device__ __forceinline__ void wave_widen(const TileArgs &a, int lane, double *
     constexpr int A = P == min_class(P0) ? 1 : 0;
     const int org = (a.w >> 1) - 32 * P;
     if constexpr (P < P0) {
-        const int cap = top < 32 * P / R - 1 ? top : 32 * P / R - 1;
+        constexpr int last = widen_switch<Sch, P0, P>() - 1;
+        const int cap = top < last ? top : last;
         if (s <= cap) {
             double r0[NV][P], r1[NV][P];
             fetch_rows<Sch, P, SPAN>(stage, org, lane, r0, r1);
@@ -597,7 +634,7 @@ __device__ __forceinline__ void wave_widen(const TileArgs &a, int lane, double *
                                                                                hr, nullptr, org, stage);
             park_rows<Sch, P, P0>(a, stage, org, lane, cap, r0, r1);
         }
-        if (cap < top) wave_widen<Sch, 2 * P, P0, WALL>(a, lane, stage, cap + 1, top, n_last, hl, hr);
+        if (cap < top) wave_widen<Sch, next_class<Sch>(P0, P), P0, WALL>(a, lane, stage, cap + 1, top, n_last, hl, hr);
     } else {
         double r0[NV][P], r1[NV][P];
         fetch_rows<Sch, P, SPAN>(stage, org, lane, r0, r1);
@@ -615,14 +652,16 @@ __device__ __forceinline__ void wave_widen(const TileArgs &a, int lane, double *
             run_segment<Sch, P, false, WALL, true, A, P0>(a, lane, 1, s, top, 0, r0, r1, hl, hr, nullptr, org, stage);
         }
         const int mtop = 2 * a.H;
-        const int s_next = P > min_class(P0) ? mtop - 16 * P / R + 1 : n_last + 1;
+        int s_next = n_last + 1;   // first level of the class below
+        if constexpr (P > min_class(P0)) s_next = narrow_switch<Sch, P0, P>(mtop);
         const int cap = n_last < s_next - 1 ? n_last : s_next - 1;
         if (top + 1 <= cap)
             run_segment<Sch, P, false, WALL, false, 1, P0, !peel_widest<Sch>()>(a, lane, 1, top + 1, cap, mtop, r0,
                                                                                 r1, hl, hr, nullptr, org, stage);
         park_rows<Sch, P, P0>(a, stage, org, lane, top + 1 <= cap ? cap : top, r0, r1);
         if constexpr (P > min_class(P0)) {
-            if (n_last >= s_next) wave_narrow<Sch, P / 2, P0, WALL>(a, lane, stage, s_next, n_last, mtop, hl, hr);
+            if (n_last >= s_next)
+                wave_narrow<Sch, prev_class<Sch>(P0, P), P0, WALL>(a, lane, stage, s_next, n_last, mtop, hl, hr);
         }
     }
 }
