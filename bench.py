@@ -208,18 +208,23 @@ def ensemble_run(count=4096, nsteps=10_000, one_at_a_time_sample=512):
             "speedup": best / alone_rate}
 
 
+# Shared-variant widths searched per scheme (two rows of nvars (w + 2 r) doubles within 160 KB)
+LDS_WIDTHS = {W.HEAT: (256, 1024, 2048, 4096, 8192), W.KS: (256, 1024, 2048, 4096, 8192),
+              W.EULER: (256, 1024, 2048)}
+
+
 def legal_p(scheme):
     return (1, 2, 4, 8) if scheme == W.EULER else (1, 2, 4, 8, 16)
 
 
-def search_shapes(sw, torch, prob, ic, shapes):
+def search_shapes(sw, torch, prob, ic, shapes, flags=0):
     """Best (rate, width, threads) of the swept solve over the given tile shapes."""
     best = None
     for w, t in shapes:
         if prob.n % w:
             continue
         try:
-            r, _, _, _ = rate_of(sw, torch, prob, ic, "swept", reps=1, width=w, threads=t)
+            r, _, _, _ = rate_of(sw, torch, prob, ic, "swept", flags=flags, reps=1, width=w, threads=t)
         except sw.SweptError:
             continue
         if best is None or r > best[0]:
@@ -264,6 +269,9 @@ def suite_sweep(schemes, log2ns, max_steps):
             same = bool(torch.equal(xs, xg))
             reg = search_shapes(sw, torch, prob, ic, [(64 * p, 64) for p in legal_p(scheme)])
             p1 = search_shapes(sw, torch, prob, ic, [(t, t) for t in (64, 128, 256, 512, 1024)])
+            # the Shared variant (rows in LDS), up to the widest tile 160 KB of LDS holds
+            lds = search_shapes(sw, torch, prob, ic, [(w, t) for w in LDS_WIDTHS[scheme] for t in (256, 1024)
+                                                      if w % t == 0], flags=sw.SW_TUNE_LDS)
             e2e_s = e2e_seconds(sw, torch, prob, ic, "swept")
             e2e_c = e2e_seconds(sw, torch, prob, ic, "classic")
             upd = prob.n * prob.nsteps
@@ -275,6 +283,7 @@ def suite_sweep(schemes, log2ns, max_steps):
                     "width": info["width"], "threads": info["threads"], "bitwise_equal": same,
                     "register_best": None if reg is None else {"rate": reg[0], "width": reg[1], "threads": reg[2]},
                     "one_point_per_thread_best": None if p1 is None else {"rate": p1[0], "width": p1[1], "threads": p1[2]},
+                    "lds_best": None if lds is None else {"rate": lds[0], "width": lds[1], "threads": lds[2]},
                     "e2e_swept": upd / e2e_s, "e2e_classic": upd / e2e_c,
                     "classic_hbm_roofline": roof, "swept_over_classic_roofline": rs / roof}
             if scheme in FLOPS_PER_POINT_LEVEL:

@@ -100,6 +100,14 @@ typedef struct {
                                  results; phases are enqueued one by one (no graph), and a solve
                                  first waits on the host for the plan's previous solve.  No
                                  effect for periodic problems. */
+#define SW_TUNE_LDS       8   /* Shared variant (Sec. 5.1): each tile's two-row working array lives
+                                 in LDS and the work-group's threads stride over every level's
+                                 points, one barrier per level, instead of the register kernel.
+                                 The width may be any multiple of 4 r up to 64 points per thread
+                                 whose rows, 2 nvars (width + 2 r) doubles, fit in 160 KB of LDS
+                                 (heat and KS: width <= 10,236; Euler: <= 3,408); otherwise
+                                 SW_EINVAL.  Bit-identical results.  Not with SW_TUNE_HYBRID or
+                                 swept_solve_noalloc. */
 typedef struct {
     int32_t width;
     int32_t threads;

@@ -16,11 +16,11 @@ from typing import Optional
 
 from . import _native as N
 from ._native import (SW_DIRICHLET, SW_EULER, SW_HEAT, SW_KS, SW_PERIODIC, SW_REFLECTIVE, SW_TUNE_CHECK_NAN,
-                      SW_TUNE_HYBRID, SW_TUNE_NO_GRAPH, SweptError, problem_struct)
+                      SW_TUNE_HYBRID, SW_TUNE_LDS, SW_TUNE_NO_GRAPH, SweptError, problem_struct)
 
 __all__ = ["Plan", "Batch", "swept_plan", "swept_solve", "classic_solve", "swept_solve_noalloc", "SweptError",
            "SW_HEAT", "SW_KS", "SW_EULER", "SW_PERIODIC", "SW_DIRICHLET", "SW_REFLECTIVE",
-           "SW_TUNE_NO_GRAPH", "SW_TUNE_CHECK_NAN", "SW_TUNE_HYBRID"]
+           "SW_TUNE_NO_GRAPH", "SW_TUNE_CHECK_NAN", "SW_TUNE_HYBRID", "SW_TUNE_LDS"]
 
 
 def _stream_handle(stream) -> Optional[int]:

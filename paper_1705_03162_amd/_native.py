@@ -18,7 +18,7 @@ SW_OK, SW_EINVAL, SW_ENOMEM, SW_EDEVICE, SW_EUNSUPPORTED, SW_EBUSY, SW_ENOTREADY
 SW_HEAT, SW_KS, SW_EULER = 0, 1, 2
 SW_PERIODIC, SW_DIRICHLET, SW_REFLECTIVE = 0, 1, 2
 SW_PROBLEM_LIMITER_RECIPROCAL = 1
-SW_TUNE_NO_GRAPH, SW_TUNE_CHECK_NAN, SW_TUNE_HYBRID = 1, 2, 4
+SW_TUNE_NO_GRAPH, SW_TUNE_CHECK_NAN, SW_TUNE_HYBRID, SW_TUNE_LDS = 1, 2, 4, 8
 SW_NOALLOC_SCRATCH_BYTES = 32 << 20
 SW_TICKET_QUEUED, SW_TICKET_RUNNING, SW_TICKET_DONE, SW_TICKET_FAILED, SW_TICKET_CANCELLED = range(5)
 

@@ -126,12 +126,19 @@ int ensure_device(sw_plan *p)
     return SW_OK;
 }
 
+// One swept phase of the plan's kernel: the register tile, or the Shared variant.
+hipError_t launch_plan_phase(const Geom &g, const TileArgs &a, hipStream_t st, int64_t tiles = -1)
+{
+    if (g.lds) return launch_lds_phase(g.scheme, g.threads, a, st, tiles);
+    return launch_swept_phase(g.scheme, g.P, g.threads, a, st, tiles);
+}
+
 int enqueue_phases(sw_plan *p, double *state, size_t first, size_t count, hipStream_t st)
 {
     const Geom &g = p->geom;
     for (size_t i = first; i < first + count; ++i) {
         TileArgs a = make_tile_args(g, p->consts, p->phases[i], state, p->d_edges);
-        hipError_t e = launch_swept_phase(g.scheme, g.P, g.threads, a, st);
+        hipError_t e = launch_plan_phase(g, a, st);
         if (e != hipSuccess) return hip_fail(e, "swept kernel launch");
     }
     return SW_OK;
@@ -221,6 +228,10 @@ int run_hybrid(sw_plan *p, double *state, hipStream_t st)
 int run_swept(sw_plan *p, double *state, hipStream_t st)
 {
     const size_t n = p->phases.size();
+    if (p->geom.lds && !p->lds_ready) {   // before any launch is captured
+        HIP_TRY(prepare_lds_phase(p->geom.scheme));
+        p->lds_ready = true;
+    }
     if (uses_hybrid(p)) {
         // the previous solve's host callbacks read the per-phase records rewritten here
         HIP_TRY(hipEventSynchronize(p->done));
@@ -356,8 +367,16 @@ int swept_plan(const sw_problem *problem, const sw_tuning *tuning, sw_plan **out
     if (width == 0) {
         if (!tuned_shape(*problem, &width, &threads)) default_shape(*problem, &width, &threads);
     }
+    const int32_t tflags = tuning ? tuning->flags : 0;
+    if (tflags & ~(SW_TUNE_NO_GRAPH | SW_TUNE_CHECK_NAN | SW_TUNE_HYBRID | SW_TUNE_LDS))
+        return fail(SW_EINVAL, "unknown tuning flags");
+    const bool lds = (tflags & SW_TUNE_LDS) != 0;
+    if (lds && (tflags & SW_TUNE_HYBRID)) return fail(SW_EINVAL, "SW_TUNE_LDS and SW_TUNE_HYBRID exclude each other");
     Geom g;
-    if ((rc = make_geom(*problem, width, threads, &g, &err))) return fail(rc, err);
+    if ((rc = make_geom(*problem, width, threads, &g, &err, lds))) return fail(rc, err);
+    if (lds && lds_tile_bytes(g.nv, g.r, g.w) > kLdsTileMaxBytes)
+        return fail(SW_EINVAL, "the Shared variant's rows do not fit in 160 KB of LDS at this width");
+
     if (tuning && tuning->width && !g.swept_ok)
         return fail(SW_EINVAL, "tile width does not divide n");
     int ct = tuning ? tuning->classic_threads : 0;
@@ -370,11 +389,7 @@ int swept_plan(const sw_problem *problem, const sw_tuning *tuning, sw_plan **out
     p->geom = g;
     p->consts = make_consts(*problem);
     if (g.swept_ok) p->phases = build_phases(g);
-    p->tflags = tuning ? tuning->flags : 0;
-    if (p->tflags & ~(SW_TUNE_NO_GRAPH | SW_TUNE_CHECK_NAN | SW_TUNE_HYBRID)) {
-        delete p;
-        return fail(SW_EINVAL, "unknown tuning flags");
-    }
+    p->tflags = tflags;
     *out = p;
     return SW_OK;
 }
@@ -423,6 +438,10 @@ int swept_profile_phase(sw_plan *p, double *d_state, int32_t kind, int32_t reps,
     if (!p->geom.swept_ok) return fail(SW_EUNSUPPORTED, "plan cannot run swept");
     double us = 0.0;
     int rc = solve_common(p, d_state, hip_stream, [&](hipStream_t st) -> int {
+        if (p->geom.lds && !p->lds_ready) {
+            HIP_TRY(prepare_lds_phase(p->geom.scheme));
+            p->lds_ready = true;
+        }
         hipEvent_t e0 = nullptr, e1 = nullptr;
         HIP_TRY(hipEventCreate(&e0));
         HIP_TRY(hipEventCreate(&e1));
@@ -431,7 +450,7 @@ int swept_profile_phase(sw_plan *p, double *d_state, int32_t kind, int32_t reps,
         for (int32_t i = 0; i < reps && r == SW_OK && he == hipSuccess; ++i) {
             Phase ph{kind, p->geom.H, kind == PH_UP ? 0 : (int32_t)((i + 1) & 1)};
             TileArgs a = make_tile_args(p->geom, p->consts, ph, d_state, p->d_edges);
-            hipError_t le = launch_swept_phase(p->geom.scheme, p->geom.P, p->geom.threads, a, st);
+            hipError_t le = launch_plan_phase(p->geom, a, st);
             if (le != hipSuccess) r = hip_fail(le, "profiled launch");
         }
         if (he == hipSuccess) he = hipEventRecord(e1, st);

@@ -17,6 +17,7 @@ struct sw_plan {
     sw::Consts consts{};
     std::vector<sw::Phase> phases;
     int tflags = 0;
+    bool lds_ready = false;       // Shared variant: kernel's LDS limit raised
     int device = -1;              // device of the scratch buffers (set on first solve)
     double *d_edges = nullptr;    // 2K edge slots
     double *d_tmp = nullptr;      // classic ping-pong / predictor buffer

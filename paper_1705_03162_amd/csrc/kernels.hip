@@ -1,13 +1,14 @@
 // HIP kernels for gfx950 besides the swept tile kernel: the classic
-// one-sub-step-per-launch kernel, the served-batch phase counter, the device
-// clock stamp and the non-finite scan, plus the dispatch of every launch by
-// scheme.  The swept tile kernel and its batched form are in swept_tile.hpp,
+// one-sub-step-per-launch kernel, the Shared-variant swept tile (lds_tile.hpp), the
+// served-batch phase counter, the device clock stamp and the non-finite scan, plus the
+// dispatch of every launch by scheme.  The swept tile kernel and its batched form are in swept_tile.hpp,
 // instantiated per scheme in tiles_heat.hip, tiles_ks.hip and tiles_euler.hip.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 
 #include "kernels.hpp"
+#include "lds_tile.hpp"
 
 namespace sw {
 
@@ -86,6 +87,22 @@ hipError_t launch_swept_phase(int scheme, int P, int threads, const TileArgs &a,
     if (scheme == 0) return swept_phase_for<Heat>(P, threads, a, st, tiles);
     if (scheme == 1) return swept_phase_for<KS>(P, threads, a, st, tiles);
     return swept_phase_for<Euler>(P, threads, a, st, tiles);
+}
+
+hipError_t prepare_lds_phase(int scheme)
+{
+    if (scheme == 0) return lds_prepare_for<Heat>();
+    if (scheme == 1) return lds_prepare_for<KS>();
+    return lds_prepare_for<Euler>();
+}
+
+hipError_t launch_lds_phase(int scheme, int threads, const TileArgs &a, hipStream_t st, int64_t tiles)
+{
+    if (tiles < 0 || tiles > a.K) tiles = a.K;
+    if (tiles <= 0) return hipSuccess;
+    if (scheme == 0) return lds_phase_for<Heat>(threads, a, st, tiles);
+    if (scheme == 1) return lds_phase_for<KS>(threads, a, st, tiles);
+    return lds_phase_for<Euler>(threads, a, st, tiles);
 }
 
 template <class Sch>

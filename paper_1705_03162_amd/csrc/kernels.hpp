@@ -12,6 +12,18 @@ namespace sw {
 hipError_t launch_swept_phase(int scheme, int P, int threads, const TileArgs &a, hipStream_t st,
                               int64_t tiles = -1);
 
+// One swept phase of the Shared variant (lds_tile.hpp): the tile's two rows in LDS,
+// `threads` lanes striding over each level's points, one barrier per level.  The rows
+// take 2 nv (w + 2 r) doubles of LDS, at most kLdsTileMaxBytes.
+constexpr int64_t kLdsTileMaxBytes = 160 * 1024;
+// LDS per work-group of the Shared variant: rows [nv][2][w + 2r] doubles, the r halo
+// positions on each side holding the neighbouring triangles' tips.
+constexpr int64_t lds_tile_bytes(int nv, int r, int w) { return (int64_t)2 * nv * (w + 2 * r) * 8; }
+hipError_t launch_lds_phase(int scheme, int threads, const TileArgs &a, hipStream_t st, int64_t tiles = -1);
+// Raise the Shared-variant kernel's dynamic LDS limit to kLdsTileMaxBytes; call before
+// the first launch (not during stream capture).
+hipError_t prepare_lds_phase(int scheme);
+
 // One classic sub-step over n points: src -> dst (in place on dst for a final RK2 stage),
 // in work-groups of `threads` lanes (a multiple of 64 in [64, 1024]).
 hipError_t launch_classic_level(int scheme, const double *src, double *dst, int64_t n, int bc,

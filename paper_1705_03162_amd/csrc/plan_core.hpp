@@ -31,6 +31,7 @@ struct Geom {
     int classic_threads = 256;   // work-group size of the classic kernel
     int64_t K = 0, Q = 0, rem = 0;
     bool swept_ok = false;
+    bool lds = false;   // Shared variant: the rows in LDS, threads striding over the points
     int64_t edge_doubles = 0;
 };
 
@@ -103,8 +104,10 @@ inline Consts make_consts(const sw_problem &p)
     return c;
 }
 
-// Geometry for an explicit tile shape (width = P * threads).
-inline int make_geom(const sw_problem &p, int width, int threads, Geom *g, std::string *err)
+// Geometry for an explicit tile shape (width = P * threads).  lds: the Shared variant,
+// whose threads stride over the tile's points in LDS (any 1 <= P <= 64; the caller
+// checks the LDS the rows take).
+inline int make_geom(const sw_problem &p, int width, int threads, Geom *g, std::string *err, bool lds = false)
 {
     Geom q;
     q.scheme = p.scheme; q.bc = p.bc;
@@ -115,11 +118,17 @@ inline int make_geom(const sw_problem &p, int width, int threads, Geom *g, std::
     if (!legal_threads(threads)) { *err = "threads must be a multiple of 64 in [64, 1024]"; return SW_EINVAL; }
     if (width <= 0 || width % threads != 0) { *err = "width must be a positive multiple of threads"; return SW_EINVAL; }
     q.P = width / threads;
-    if (!legal_points_per_lane(p.scheme, q.P)) {
+    q.lds = lds;
+    if (lds) {
+        if (q.P > 64 || width % (4 * q.r) != 0) {
+            *err = "Shared-variant width must be at most 64 points per thread and a multiple of 4 r";
+            return SW_EINVAL;
+        }
+    } else if (!legal_points_per_lane(p.scheme, q.P)) {
         *err = "width/threads must be 1, 2, 4, 8 or 16 points per lane, at least the stencil radius (Euler: at most 8)";
         return SW_EINVAL;
     }
-    if (threads > max_threads_for(scheme_nvars(p.scheme), q.P)) {
+    if (!lds && threads > max_threads_for(scheme_nvars(p.scheme), q.P)) {
         *err = "threads too large for this scheme and points per lane";
         return SW_EINVAL;
     }

@@ -173,6 +173,31 @@ def test_hybrid_flag_accepted_and_unknown_flags_rejected(lib):
     assert rc == N.SW_EINVAL
 
 
+def test_lds_variant_shapes(lib):
+    """SW_TUNE_LDS (the Shared variant) takes widths the register kernel cannot (any number
+    of points per thread up to 64) as long as the two rows fit in 160 KB of LDS, and it
+    excludes the Hybrid variant and the allocation-free solve."""
+    heat = W.heat_problem(1 << 16, 10)
+    rc, h = _plan(lib, heat, 8192, 1024, flags=N.SW_TUNE_LDS)
+    assert rc == 0
+    i = _info(lib, h)
+    assert (i.width, i.threads, i.points_per_lane) == (8192, 1024, 8)
+    lib.swept_plan_destroy(h)
+    assert _plan(lib, heat, 8192, 1024)[0] == N.SW_EINVAL                   # register budget
+    assert _plan(lib, heat, 16384, 1024, flags=N.SW_TUNE_LDS)[0] == N.SW_EINVAL   # 262 KB of rows
+    assert b"160 KB" in lib.sw_last_error()
+    assert _plan(lib, heat, 8192, 64, flags=N.SW_TUNE_LDS)[0] == N.SW_EINVAL      # 128 points per thread
+    sod = W.sod_problem(1 << 14, 10)
+    assert _plan(lib, sod, 4096, 1024, flags=N.SW_TUNE_LDS)[0] == N.SW_EINVAL     # 3 variables: 197 KB
+    rc, h = _plan(lib, sod, 2048, 1024, flags=N.SW_TUNE_LDS)
+    assert rc == 0
+    lib.swept_plan_destroy(h)
+    assert _plan(lib, sod, 2048, 1024, flags=N.SW_TUNE_LDS | N.SW_TUNE_HYBRID)[0] == N.SW_EINVAL
+    ok = N.problem_struct(W.ks_problem(1 << 20, 10))
+    t = N.SwTuning(1024, 64, N.SW_TUNE_LDS)
+    assert lib.swept_solve_noalloc(ctypes.byref(ok), ctypes.byref(t), None, None) == N.SW_EINVAL
+
+
 def test_tuned_shapes_from_nearest_measured_class(lib):
     """Sizes the table measured take their row; larger sizes take the largest measured
     class, smaller ones the smallest, as long as that width divides n."""

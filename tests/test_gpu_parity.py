@@ -431,3 +431,31 @@ def test_hybrid_repeated_solves_on_one_plan():
         torch.cuda.synchronize()
     assert torch.equal(a, b)
     assert np.array_equal(a.cpu().numpy(), gpu_solve(prob, ic, "swept", 512, 64))
+
+
+# ---------------------------------------------------------------- Shared variant (rows in LDS)
+
+LDS_CASES = [  # (problem factory, width, threads): remainders, walls, and widths near 160 KB of LDS
+    (lambda: (W.heat_problem(4096, 1777), W.fourier_ic(4096, 31)), 1024, 256),
+    (lambda: (W.heat_problem(3072, 1201, bc=W.DIRICHLET, bc_left=0.3, bc_right=-0.7),
+              W.fourier_ic(3072, 32)), 512, 128),
+    (lambda: (W.heat_problem(2048, 1313, bc=W.REFLECTIVE), W.fourier_ic(2048, 33)), 1024, 1024),
+    (lambda: (W.heat_problem(20352, 9000), W.fourier_ic(20352, 34)), 10176, 192),      # 162,848 B of LDS
+    (lambda: (W.ks_problem(8192, 555), W.fourier_ic(8192, 35)), 2048, 512),
+    (lambda: (W.Problem(W.KS, 3072, 421, 2.0 ** -8, 0.5, bc=W.DIRICHLET, bc_left=(0.4, 0, 0),
+                        bc_right=(-0.2, 0, 0)), W.fourier_ic(3072, 36)), 1024, 64),
+    (lambda: (W.sod_problem(2048, 777), W.sod_ic(2048)), 1024, 256),
+    (lambda: (W.sod_problem(6656, 1500), W.sod_ic(6656)), 3328, 256),                  # 159,936 B of LDS
+]
+
+
+@pytest.mark.parametrize("case", range(len(LDS_CASES)))
+def test_lds_variant_matches_classic_bitwise_and_oracle(oracle_mod, case):
+    """The Shared variant (SW_TUNE_LDS: each tile's two rows in LDS, threads striding over
+    the points, one barrier per level) gives the register kernel's and classic's bits."""
+    factory, width, threads = LDS_CASES[case]
+    prob, ic = factory()
+    lds = gpu_solve(prob, ic, "swept", width, threads, flags=sw.SW_TUNE_LDS)
+    classic = gpu_solve(prob, ic, "classic")   # (the register kernel cannot take every LDS width)
+    assert np.array_equal(lds, classic)
+    assert relerr(lds, oracle_mod.solve(prob, ic)) <= TOL
