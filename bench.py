@@ -759,6 +759,25 @@ def main():
                 "traffic_source": TRAFFIC_SUMMARY if traffic is not None else None,
                 "kernel_digest": kernel_digest()}
 
+    # ---- the paper's insulated heat case with end-to-end times (plan, allocation, copies in
+    # and out), and the Euler/Sod verdict, swept against classic at the same size
+    log("insulated heat and Sod at 2^20 ...")
+    extra = {}
+    hp = W.heat_problem(n, NSTEPS, bc=W.REFLECTIVE)
+    hic = W.fourier_ic(n, seed=2 + LOG2N)
+    rs, _, _, _ = rate_of(sw, torch, hp, hic, "swept", reps=2)
+    rc, _, _, _ = rate_of(sw, torch, hp, hic, "classic", reps=1)
+    upd_h = hp.n * hp.nsteps
+    extra["heat_insulated"] = {"n": hp.n, "steps": hp.nsteps, "swept": rs, "classic_graph": rc,
+                               "swept_e2e": upd_h / e2e_seconds(sw, torch, hp, hic, "swept"),
+                               "classic_e2e": upd_h / e2e_seconds(sw, torch, hp, hic, "classic")}
+    sp, sic = W.cfg_sod(LOG2N, nsteps=20_000)
+    rs, _, _, xs = rate_of(sw, torch, sp, sic, "swept", reps=1)
+    rc, _, _, xc = rate_of(sw, torch, sp, sic, "classic", reps=1)
+    extra["sod"] = {"n": sp.n, "steps": sp.nsteps, "swept": rs, "classic_graph": rc,
+                    "swept_over_classic": rs / rc, "bitwise_equal": bool(torch.equal(xs, xc)),
+                    "verdict": "swept faster" if rs > rc else "classic faster"}
+
     result = {
         "metric": METRIC, "value": value, "unit": "point-updates/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": t_step * 1e3,
@@ -775,6 +794,7 @@ def main():
         "per_scheme": per_scheme,
         "swept_equals_classic_bitwise": bool(bitwise),
         "roofline": roofline,
+        "variants": extra,
     }
     for pl in plans:
         pl.close()
