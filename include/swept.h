@@ -250,7 +250,8 @@ int  batch_submit_async(sw_batch *batch, const sw_problem *problem, double *d_st
 /* Ensemble mode: run every queued solve to completion, then return
  * (synchronous).  Solves are admitted in submission order in waves that fit the
  * budget and slot limit; each wave runs as one HIP graph launch holding one
- * batched launch per phase index and tile-width group. */
+ * batched launch per phase index and tile-width group, each group's chain of
+ * launches on a parallel branch of the graph. */
 int  batch_run(sw_batch *batch, void *hip_stream);
 int  batch_poll(sw_batch *batch, uint64_t ticket, int32_t *status_out);
 /* Block until the ticket is done, cancelled or failed, or timeout_us passes

@@ -284,24 +284,32 @@ struct EnsembleRun {
 // Relative cost of a point-level (for splitting the persistent grid between groups).
 double level_weight(int scheme) { return scheme == SW_EULER ? 20.0 : (scheme == SW_KS ? 2.0 : 1.0); }
 
-// Capture the phase-index launches of every group (one launch per phase index and
-// group, timing stamps after each phase index).
-int capture_lockstep(EnsembleRun &run, uint64_t *d_stamps, int max_phases, hipGraph_t *graph)
+// Capture the phase-index launches of every group: each group's chain of launches (one
+// per phase index, then a timing stamp) on a parallel branch of the graph, so a group of
+// short phases runs beside the others instead of waiting for each phase index of all.
+int capture_lockstep(EnsembleRun &run, uint64_t *d_stamps, const std::vector<size_t> &soff, hipGraph_t *graph)
 {
     BHIP(hipStreamBeginCapture(run.cap, hipStreamCaptureModeThreadLocal));
     hipError_t le = launch_stamp(d_stamps, 0, run.cap);
-    for (int p = 0; p < max_phases && le == hipSuccess; ++p) {
-        for (GroupBuf &g : run.gb) {
+    hipEvent_t fork = run.events[0];
+    if (le == hipSuccess) le = hipEventRecord(fork, run.cap);
+    for (size_t g = 0; g < run.gb.size() && le == hipSuccess; ++g) {
+        GroupBuf &gb = run.gb[g];
+        hipStream_t s = run.streams[g];
+        if ((le = hipStreamWaitEvent(s, fork, 0)) != hipSuccess) break;
+        const int gp = gb.desc.empty() ? 0 : gb.desc.front().nphases;   // sorted: the largest first
+        size_t a = gb.desc.size();
+        for (int p = 0; p < gp && le == hipSuccess; ++p) {
             // solves still running at phase p: a prefix of the sorted group
-            size_t a = 0;
-            while (a < g.desc.size() && g.desc[a].nphases > p) ++a;
-            const int64_t nitems = g.prefix[a];
-            if (nitems == 0) continue;
-            const int grid = (int)std::min<int64_t>(nitems, g.grid_cap);
-            le = launch_batch_phase(g.scheme, g.P, g.d_desc, g.d_items, nitems, p, grid, run.cap);
-            if (le != hipSuccess) break;
+            while (a > 0 && gb.desc[a - 1].nphases <= p) --a;
+            const int64_t nitems = gb.prefix[a];
+            const int grid = (int)std::min<int64_t>(nitems, gb.grid_cap);
+            le = launch_batch_phase(gb.scheme, gb.P, gb.d_desc, gb.d_items, nitems, p, grid, s);
+            if (le == hipSuccess) le = launch_stamp(d_stamps, (int)(soff[g] + (size_t)p), s);
         }
-        if (le == hipSuccess) le = launch_stamp(d_stamps, p + 1, run.cap);
+        if (le != hipSuccess) break;
+        if ((le = hipEventRecord(run.events[g + 1], s)) != hipSuccess) break;
+        le = hipStreamWaitEvent(run.cap, run.events[g + 1], 0);
     }
     hipError_t ce = hipStreamEndCapture(run.cap, graph);
     if (le != hipSuccess) return hip_fail(le, "batched phase launch");
@@ -356,18 +364,21 @@ int run_ensemble(sw_batch *b, std::vector<Ticket *> &ts, hipStream_t st)
     int rc = SW_OK;
     const bool persistent = (b->cfg.flags & SW_BATCH_PERSISTENT) != 0;
     std::vector<PersistGroup> pg;
-    uint64_t *d_stamps = nullptr;   // lock-step: per phase index; persistent: [0] = start
+    // timing stamps: [0] = start, then per group from soff[g]: one per phase index
+    // (lock-step) or one per solve (persistent)
+    std::vector<size_t> soff;
+    uint64_t *d_stamps = nullptr;
     std::vector<uint64_t> stamps;
-    int max_phases = 0, clock_khz = 0;
+    int clock_khz = 0;
     double t0 = 0.0;
     auto finish = [&](int code) {
         if (code == SW_OK) {
             const double tick_s = clock_khz > 0 ? 1.0 / (1000.0 * clock_khz) : 0.0;
-            size_t k = 0;
             for (size_t g = 0; g < run.gb.size(); ++g)
-                for (size_t i = 0; i < run.gb[g].members.size(); ++i, ++k) {
+                for (size_t i = 0; i < run.gb[g].members.size(); ++i) {
                     Ticket *t = run.gb[g].members[i];
-                    const uint64_t end = persistent ? stamps[1 + k] : stamps[(size_t)phase_count(t->geom.Q, t->geom.rem)];
+                    const size_t np = (size_t)phase_count(t->geom.Q, t->geom.rem);
+                    const uint64_t end = persistent ? stamps[soff[g] + i] : (np ? stamps[soff[g] + np - 1] : stamps[0]);
                     t->t_end = t0 + (double)(end - stamps[0]) * tick_s;
                     t->status = SW_TICKET_DONE;
                 }
@@ -405,7 +416,6 @@ int run_ensemble(sw_batch *b, std::vector<Ticket *> &ts, hipStream_t st)
             g.desc.push_back(make_desc(*v[s]));
             for (int64_t j = 0; j < v[s]->geom.K; ++j) g.items.push_back(make_int2((int)s, (int)j));
             g.prefix.push_back((int64_t)g.items.size());
-            max_phases = std::max(max_phases, g.desc.back().nphases);
         }
         g.grid_cap = batch_blocks_per_cu(g.scheme, g.P) * num_cus();
         run.gb.push_back(std::move(g));
@@ -416,7 +426,13 @@ int run_ensemble(sw_batch *b, std::vector<Ticket *> &ts, hipStream_t st)
             hipDeviceGetAttribute(&clock_khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess)
             return finish(fail(SW_EDEVICE, "device clock rate"));
     }
-    const size_t nstamps = persistent ? 1 + ts.size() : (size_t)max_phases + 1;
+    size_t nstamps = 1;
+    soff.assign(run.gb.size(), 0);
+    for (size_t g = 0; g < run.gb.size(); ++g) {
+        soff[g] = nstamps;
+        nstamps += persistent ? run.gb[g].desc.size()
+                              : (run.gb[g].desc.empty() ? 0 : (size_t)run.gb[g].desc.front().nphases);
+    }
     stamps.assign(nstamps, 0);
     if (run.alloc((void **)&d_stamps, nstamps * sizeof(uint64_t)) != hipSuccess)
         return finish(fail(SW_ENOMEM, "stamp buffer allocation failed"));
@@ -438,7 +454,6 @@ int run_ensemble(sw_batch *b, std::vector<Ticket *> &ts, hipStream_t st)
             total_work += work[g];
         }
         pg.resize(run.gb.size());
-        size_t stamp_off = 1;
         for (size_t g = 0; g < run.gb.size(); ++g) {
             GroupBuf &gb = run.gb[g];
             PersistGroup &x = pg[g];
@@ -467,17 +482,18 @@ int run_ensemble(sw_batch *b, std::vector<Ticket *> &ts, hipStream_t st)
             x.q.phase_start = d_ps;
             x.q.done = d_done;
             x.q.finished = d_fin;
-            x.q.stamps = d_stamps + stamp_off;
+            x.q.stamps = d_stamps + soff[g];
             x.q.next = d_next;
             x.q.error = d_err;
             x.q.max_phases = gp;
             x.q.spin_limit = (int64_t)1 << 22;   // a few seconds of polling
-            stamp_off += gb.desc.size();
             const int occ = persistent_blocks_per_cu(gb.scheme, gb.P) * num_cus();
             const double share = total_work > 0.0 ? work[g] / total_work : 1.0;
             x.grid = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)(occ * share + 0.5),
                                                                  std::max<int64_t>(x.phase_start.back(), 1)));
         }
+    }
+    {   // fork streams and events of the parallel branches
         run.streams.assign(run.gb.size(), nullptr);
         run.events.assign(run.gb.size() + 1, nullptr);
         for (hipStream_t &s : run.streams)
@@ -491,7 +507,7 @@ int run_ensemble(sw_batch *b, std::vector<Ticket *> &ts, hipStream_t st)
         return finish(fail(SW_EDEVICE, "capture stream creation"));
     }
     hipGraph_t graph = nullptr;
-    rc = persistent ? capture_persistent(run, pg, d_stamps, &graph) : capture_lockstep(run, d_stamps, max_phases, &graph);
+    rc = persistent ? capture_persistent(run, pg, d_stamps, &graph) : capture_lockstep(run, d_stamps, soff, &graph);
     if (rc == SW_OK) {
         hipError_t e = hipGraphInstantiate(&run.exec, graph, nullptr, nullptr, 0);
         if (e != hipSuccess) { run.exec = nullptr; rc = hip_fail(e, "hipGraphInstantiate"); }

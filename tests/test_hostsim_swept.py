@@ -28,9 +28,9 @@ LIB = os.path.join(HERE, "hostsim", "libhostsim.so")
 def build_hostsim():
     cmd = ["g++", "-O2", "-std=c++17", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
            "-Wno-unknown-pragmas", "-I", os.path.join(ROOT, "include"),
-           "-I", os.path.join(ROOT, "paper_1705_03162_amd", "csrc"), SRC, HYBRID_SRC, "-o", LIB + ".tmp"]
+           "-I", os.path.join(ROOT, "paper_1705_03162_amd", "csrc"), SRC, HYBRID_SRC, "-o", f"{LIB}.{os.getpid()}.tmp"]
     subprocess.run(cmd, check=True)
-    os.replace(LIB + ".tmp", LIB)
+    os.replace(f"{LIB}.{os.getpid()}.tmp", LIB)
 
 
 @pytest.fixture(scope="module")
