@@ -146,14 +146,27 @@ def peak_resident(infos, sizes):
 
 
 def test_ensemble_equals_oracle(sim, oracle_mod):
-    """Ensemble mode (one captured graph per wave of admitted solves): mixed schemes,
-    sizes and boundaries, each result equal to the oracle."""
+    """Ensemble mode (one captured graph per wave of admitted solves, each tile group's
+    launches on a branch of its own): mixed schemes, sizes and boundaries, each result
+    equal to the oracle; within a group a solve of more phases completes later (its
+    stamp is a later one of the same branch) and solves of as many phases together."""
     probs = mixed(14, seed=21)
     states = [ic.copy() for _, ic in probs]
     b = SimBatch(sim, budget=1 << 30)
     tickets = [b.submit(p, x) for (p, _), x in zip(probs, states)]
     assert sim.batch_run(b.h, None) == 0
-    assert all(b.poll(t) == N.SW_TICKET_DONE for t in tickets)
+    infos = [b.info(t) for t in tickets]
+    assert all(i["status"] == N.SW_TICKET_DONE for i in infos)
+    assert all(i["end_s"] >= i["start_s"] for i in infos)
+    groups = {}
+    for (p, _), i in zip(probs, infos):
+        if i["swept"]:
+            groups.setdefault((p.scheme, i["width"]), []).append((i["phases"], i["end_s"]))
+    assert any(len(v) > 1 for v in groups.values())
+    for v in groups.values():
+        v.sort()
+        for (pa, ea), (pb, eb) in zip(v, v[1:]):
+            assert eb > ea if pb > pa else eb == ea, v
     b.close()
     for (prob, ic), x in zip(probs, states):
         assert np.array_equal(x, oracle_mod.solve(prob, ic)), (prob.scheme, prob.n, prob.nsteps, prob.bc)
