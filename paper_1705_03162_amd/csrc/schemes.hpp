@@ -19,9 +19,6 @@
 // 8- and 16-point ones (swept_tile.hpp, next_class); on for KS, where it cuts the lane
 // slots of the widest levels (heat's select-free 16-point levels already cost about as
 // little as selecting 12-point ones, and a class change more).
-// CLASS1: one-wave tiles run the narrowest levels (r m + r <= 32) one point per lane
-// instead of two; on for Euler, whose per-point cost (divisions and square roots in
-// every flux) outweighs a class change, off for heat and KS, where it does not.
 //
 //   Heat  (Appendix B, Eq. Heatdisc):  T' = Fo (T_{i+1} + T_{i-1}) + (1 - 2 Fo) T_i,
 //         the Fo product fused with the addition
@@ -69,7 +66,6 @@ struct Heat {
     static constexpr bool SELECT_ONE_WAVE = true;
     static constexpr bool FREE_ONE_WAVE = true;
     static constexpr bool CLASS12 = false;          // measured slower: 110.7 vs 109.3 us at 2^20
-    static constexpr bool CLASS1 = false;
     static constexpr bool LANE_EXCHANGE = false;    // no per-cell quantity shared by neighbours
     template <int P, bool SEL = true>
     SW_HD static void level(double (&dst)[NV][P], const double (&ext)[NV][P + 2 * R],
@@ -96,7 +92,6 @@ struct KS {
     static constexpr bool SELECT_ONE_WAVE = true;
     static constexpr bool FREE_ONE_WAVE = false;   // measured slower: 122.4 vs 121.6 us at 2^20, 895 vs 823 at 2^23
     static constexpr bool CLASS12 = true;
-    static constexpr bool CLASS1 = false;
     static constexpr bool LANE_EXCHANGE = false;
     // g_i(v) = -f_i(v) = (v_{i+1}^2 - v_{i-1}^2)/(4dx) + (v_{i+1} + v_{i-1} - 2v_i)/dx^2
     //                   + (v_{i+2} + v_{i-2} - 4(v_{i+1} + v_{i-1}) + 6v_i)/dx^4,
@@ -137,7 +132,6 @@ struct Euler {
     // Pressures, pressure ratios and interface fluxes belong to cells and interfaces, so
     // a lane may take its neighbours' values instead of evaluating them on its halo.
     static constexpr bool CLASS12 = false;   // its tuned tiles have at most 8 points per lane
-    static constexpr bool CLASS1 = true;
     static constexpr bool LANE_EXCHANGE = true;
 
     // Eq. EulerP with E the total energy per volume: P = (gamma-1)(E - (m u)/2), u = m/rho.

@@ -488,8 +488,8 @@ __device__ __forceinline__ void run_levels(const TileArgs &a, int g, int NW, dou
 // of the lanes idle on average (the idle threads of the paper's Results).  A
 // one-wave tile therefore keeps both rows of the whole tile in LDS and holds in
 // registers only a class layout: the 64 P points [w/2 - 32 P, w/2 + 32 P) centred
-// in the tile, lane g owning P consecutive ones, with P the smallest class (1 for a
-// scheme with CLASS1, 2, 4, 8, and for 16-point tiles 12 and 16) whose layout holds the level's computed set and
+// in the tile, lane g owning P consecutive ones, with P the smallest class (1, 2, 4, 8,
+// and for 16-point tiles 12 and 16) whose layout holds the level's computed set and
 // its halo, r m + r <= 32 P.  At a change of class the lanes park their rows in LDS and fetch
 // the next layout; positions outside the layout keep their values there (inserted
 // edges not yet reached by a widening set, finished values left behind by a
@@ -500,8 +500,7 @@ __device__ __forceinline__ void run_levels(const TileArgs &a, int g, int NW, dou
 // LDS position of tile point x: x + x/16 (one padding double per 16), which keeps
 // the stride-P accesses of every class layout and the point-major passes free of
 // bank conflicts.
-template <class Sch>
-constexpr int min_class(int P0) { return P0 < 2 ? P0 : (Sch::CLASS1 ? 1 : 2); }
+constexpr int kMinClass = 1;   // the narrowest levels (r m + r <= 32) run one point per lane
 // The classes above and below P.  Tiles of 16 points per lane of a scheme with CLASS12
 // have a 12-point class between 8 and 16: the levels with 256 < r m + r <= 384 then run
 // at three quarters of the widest class's lane slots.
@@ -595,7 +594,7 @@ __device__ __forceinline__ void wave_narrow(const TileArgs &a, int lane, double 
 {
     constexpr int NV = Sch::NV, R = Sch::R, SPAN = wave_span(P0);
     int s_next = s_last + 1;   // first level of the class below
-    if constexpr (P > min_class<Sch>(P0)) s_next = narrow_switch<Sch, P0, P>(mtop);
+    if constexpr (P > kMinClass) s_next = narrow_switch<Sch, P0, P>(mtop);
     const int cap = s_last < s_next - 1 ? s_last : s_next - 1;
     if (s <= cap) {
         const int org = (a.w >> 1) - 32 * P;
@@ -605,7 +604,7 @@ __device__ __forceinline__ void wave_narrow(const TileArgs &a, int lane, double 
                                                                              hr, nullptr, org, stage);
         park_rows<Sch, P, P0>(a, stage, org, lane, cap, r0, r1);
     }
-    if constexpr (P > min_class<Sch>(P0)) {
+    if constexpr (P > kMinClass) {
         if (s_last >= s_next)
             wave_narrow<Sch, prev_class<Sch>(P0, P), P0, WALL>(a, lane, stage, s > s_next ? s : s_next, s_last, mtop,
                                                           hl, hr);
@@ -623,7 +622,7 @@ __device__ __forceinline__ void wave_widen(const TileArgs &a, int lane, double *
                                            const double (&hr)[Sch::NV][Sch::R])
 {
     constexpr int NV = Sch::NV, R = Sch::R, SPAN = wave_span(P0);
-    constexpr int A = P == min_class<Sch>(P0) ? 1 : 0;
+    constexpr int A = P == kMinClass ? 1 : 0;
     const int org = (a.w >> 1) - 32 * P;
     if constexpr (P < P0) {
         constexpr int last = widen_switch<Sch, P0, P>() - 1;
@@ -654,13 +653,13 @@ __device__ __forceinline__ void wave_widen(const TileArgs &a, int lane, double *
         }
         const int mtop = 2 * a.H;
         int s_next = n_last + 1;   // first level of the class below
-        if constexpr (P > min_class<Sch>(P0)) s_next = narrow_switch<Sch, P0, P>(mtop);
+        if constexpr (P > kMinClass) s_next = narrow_switch<Sch, P0, P>(mtop);
         const int cap = n_last < s_next - 1 ? n_last : s_next - 1;
         if (top + 1 <= cap)
             run_segment<Sch, P, false, WALL, false, 1, P0, !peel_widest<Sch>()>(a, lane, 1, top + 1, cap, mtop, r0,
                                                                                 r1, hl, hr, nullptr, org, stage);
         park_rows<Sch, P, P0>(a, stage, org, lane, top + 1 <= cap ? cap : top, r0, r1);
-        if constexpr (P > min_class<Sch>(P0)) {
+        if constexpr (P > kMinClass) {
             if (n_last >= s_next)
                 wave_narrow<Sch, prev_class<Sch>(P0, P), P0, WALL>(a, lane, stage, s_next, n_last, mtop, hl, hr);
         }
@@ -752,8 +751,8 @@ __device__ __forceinline__ void wave_tile(const TileArgs &args, int64_t j, int l
     } else {
         const int top = a.kind == PH_DOWN ? nlev : a.H;
         const int n_last = a.kind == PH_DIAMOND ? nlev : 0;
-        if (wall) wave_widen<Sch, min_class<Sch>(P0), P0, true>(a, lane, stage, 1, top, n_last, hl, hr);
-        else wave_widen<Sch, min_class<Sch>(P0), P0, false>(a, lane, stage, 1, top, n_last, hl, hr);
+        if (wall) wave_widen<Sch, kMinClass, P0, true>(a, lane, stage, 1, top, n_last, hl, hr);
+        else wave_widen<Sch, kMinClass, P0, false>(a, lane, stage, 1, top, n_last, hl, hr);
     }
     // every class parked its rows: the stage holds both final rows of the whole tile;
     // new L slot into a (points [0, w/2 + r)), new R slot into b (points [w/2 - r, w))
