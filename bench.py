@@ -593,6 +593,8 @@ def main():
                     help="kernel suite: scheme of the profiled Diamond (N = 2^20; euler: the Sod tube)")
     ap.add_argument("--kernel-width", type=int, default=0, help="kernel suite: tile width (0 = tuned)")
     ap.add_argument("--kernel-threads", type=int, default=0, help="kernel suite: work-group size (0 = tuned)")
+    ap.add_argument("--kernel-lds", action="store_true",
+                    help="kernel suite: the Shared variant (rows in LDS; give --kernel-width/--kernel-threads)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the multi-GPU "
@@ -601,6 +603,9 @@ def main():
     if args.suite == "kernel":
         # for hardware-counter runs: a known-size device copy (calibrates FETCH/WRITE)
         # and a few launches of the dominant kernel (KS Diamond at N = 2^20)
+        if args.kernel_lds and (args.kernel_width <= 0 or args.kernel_threads <= 0):
+            print("--kernel-lds needs --kernel-width and --kernel-threads", file=sys.stderr)
+            sys.exit(2)
         import torch
         import paper_1705_03162_amd as sw
         src = torch.ones(1 << 25, dtype=torch.float64, device="cuda")   # 256 MiB
@@ -611,7 +616,8 @@ def main():
             prob, ic = W.cfg_sod(LOG2N, nsteps=2000)
         else:
             prob, ic = W.cfg_sweep({"ks": W.KS, "heat": W.HEAT}[args.kernel_scheme], LOG2N)
-        with sw.Plan(prob, args.kernel_width, args.kernel_threads) as plan:
+        flags = sw.SW_TUNE_LDS if args.kernel_lds else 0
+        with sw.Plan(prob, args.kernel_width, args.kernel_threads, flags=flags) as plan:
             x = torch.tensor(ic, dtype=torch.float64, device="cuda")
             if args.kernel_scheme == "euler":
                 plan.swept(x)   # the Diamonds then read edges of a developed Sod state
@@ -619,6 +625,7 @@ def main():
             info = plan.info()
         flops = prob.n * info["levels_per_phase"] * FLOPS_PER_POINT_LEVEL[prob.scheme]
         print(json.dumps({"copy_bytes": 2 * src.numel() * 8, "diamond_avg_us": us, "scheme": args.kernel_scheme,
+                          "variant": "lds" if args.kernel_lds else "register",
                           "width": info["width"], "threads": info["threads"],
                           "levels_per_phase": info["levels_per_phase"], "n": prob.n,
                           "flops_per_launch": flops, "tflops": flops / (us * 1e-6) / 1e12,
