@@ -255,7 +255,7 @@ Ticket *find_ticket(sw_batch *b, uint64_t id)
 struct EnsembleRun {
     std::vector<GroupBuf> gb;
     std::vector<void *> dev;           // device allocations
-    std::vector<hipStream_t> streams;  // fork streams of the persistent launch
+    std::vector<hipStream_t> streams;  // one per tile group: the graph's parallel branches
     std::vector<hipEvent_t> events;
     hipStream_t cap = nullptr;
     hipGraphExec_t exec = nullptr;
